@@ -1,0 +1,61 @@
+"""Input generators: canonical CSR invariants and pinned workload hashes."""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy.sparse.csgraph import connected_components
+
+from paper_1903_09422_amd import graphs as G
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def check_canonical(g, connected=True):
+    rp, col = g.row_ptr, g.col
+    assert rp.dtype == np.int32 and col.dtype == np.int32
+    assert rp[0] == 0 and np.all(np.diff(rp) >= 0) and rp[-1] == col.size
+    src = np.repeat(np.arange(g.n), np.diff(rp))
+    assert np.all(src != col)                      # no self-loops
+    for v in range(0, g.n, max(1, g.n // 2000)):   # rows strictly ascending
+        row = col[rp[v]:rp[v + 1]]
+        assert np.all(np.diff(row) > 0)
+    a = g.to_scipy()
+    assert (a != a.T).nnz == 0                     # symmetric
+    if connected:
+        assert connected_components(a, directed=False)[0] == 1
+
+
+@pytest.mark.parametrize("name", sorted(G.WORKLOADS))
+def test_workloads_match_manifest(name):
+    with open(os.path.join(GOLDEN, "graphs_manifest.json")) as f:
+        want = json.load(f)[name]
+    g, eps, delta, n_check = G.workload(name)
+    check_canonical(g)
+    assert (g.n, g.num_arcs, int(g.degrees().max())) == (want["n"], want["arcs"], want["max_degree"])
+    assert g.sha256() == want["sha256"]
+    assert (eps, delta, n_check) == (want["eps"], want["delta"], want["check_interval"])
+
+
+def test_small_generators_canonical():
+    for g in (G.path_graph(5), G.cycle_graph(7), G.star_graph(4), G.complete_graph(5),
+              G.complete_bipartite(2, 3), G.grid_graph(3, 4), G.hypercube(3), G.barbell(4, 2),
+              G.random_connected(30, 20, seed=1)):
+        check_canonical(g)
+    check_canonical(G.disjoint_union(G.path_graph(3), G.star_graph(3)), connected=False)
+
+
+def test_from_edges_canonicalises():
+    g = G.from_edges(6, [0, 1, 1, 2, 3, 5, 5], [1, 0, 1, 3, 2, 4, 4], lcc=False)
+    assert g.num_edges == 3
+    check_canonical(g, connected=False)
+    h = G.from_edges(6, [0, 1, 1, 2, 3, 5, 5], [1, 0, 1, 3, 2, 4, 4], lcc=True)
+    assert h.n == 2 and h.num_edges == 1  # first largest component: {0, 1}
+
+
+def test_generator_sizes():
+    g = G.perturbed_grid(32, seed=3, lcc=False)
+    e = 2 * 32 * 31
+    assert g.num_edges == e - round(0.05 * e) + round(0.001 * e)
+    r = G.rmat(10, 8, seed=2, lcc=False)
+    assert r.n == 1024 and r.num_edges <= 8 * 1024
