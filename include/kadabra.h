@@ -1,0 +1,180 @@
+/*
+ * kadabra.h -- C ABI of the MI355X (gfx950) KADABRA adaptive-sampling
+ * betweenness-centrality library.
+ *
+ * Method (van der Grinten, Angriman, Meyerhenke, "Parallel Adaptive Sampling
+ * with almost no Synchronization"):
+ *   - Algorithm 1: draw samples, aggregate them with an associative operator,
+ *     and check a stopping condition on a consistent state only;
+ *   - Section 2.3: a KADABRA sample is a uniformly random vertex pair (s, t)
+ *     and a uniformly random shortest s-t path; b~(v) = (1/tau) * number of
+ *     sampled paths with v as an interior vertex; sampling stops once
+ *     f, g <= eps for every vertex (Appendix B) or after omega samples;
+ *   - Appendix C.1: same-component test; paths rebuilt from the graph and
+ *     distance vectors; Appendix C.2: the check runs every N samples;
+ *   - Appendix D (indexed frames): sample i draws its randomness from its
+ *     index only, so the result does not depend on the parallel schedule.
+ *
+ * Determinism contract: the result (tau and every counter) is a pure function
+ * of (graph, eps, delta, seed, check_interval).  No other parameter set with
+ * kadabra_set_param changes it.
+ *
+ * Every int-returning call returns KADABRA_OK (0) or a negative status and
+ * then sets a thread-local message readable with kadabra_last_error().
+ * A handle must not be used by two threads at once; distinct handles may be.
+ */
+#ifndef KADABRA_H
+#define KADABRA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    KADABRA_OK = 0,
+    KADABRA_EINVAL = -1,    /* malformed argument or graph */
+    KADABRA_ENOMEM = -2,    /* device or host allocation failed */
+    KADABRA_EDEVICE = -3,   /* HIP runtime error or device-side invariant failure */
+    KADABRA_ESTATE = -4,    /* no completed run to read */
+    KADABRA_ERANGE = -5,    /* n, arc count, degree or omega beyond the supported limits */
+    KADABRA_ECANCELED = -6  /* kadabra_cancel() stopped the run */
+};
+
+typedef struct kadabra_graph kadabra_graph; /* opaque: device CSR, run state, last result */
+
+typedef struct {
+    int64_t tau;           /* samples drawn (a check boundary, or omega) */
+    int64_t omega;         /* maximal number of samples (Section 2.3) */
+    int64_t vd_bound;      /* vertex-diameter bound used for omega */
+    int64_t epochs;        /* check boundaries reached */
+    int64_t decision;      /* 1: stopping rule met; 2: omega reached */
+    /* algorithmic work, summed over the tau samples (independent of mapping) */
+    int64_t v_exp;         /* frontier vertices expanded */
+    int64_t e_scan;        /* arcs scanned by expansions: traversed edges */
+    int64_t v_new;         /* vertices newly reached */
+    int64_t e_pred;        /* predecessor arcs summed into sigma */
+    int64_t e_bt;          /* arcs scanned while backtracking */
+    int64_t path_interior; /* counter increments */
+    int64_t disconnected;  /* samples with s, t in different components */
+    double log_inv_delta;  /* L = log(1/delta_L) = log(4 n / delta) */
+    double ms_sampling;    /* device time from the first sampling launch to the last check */
+    double ms_total;       /* host wall time of kadabra_run */
+    double ms_sample_kernels; /* summed HIP-event durations of the sampling launches whose
+                                 samples count (epochs 1 .. epochs) */
+    int64_t sample_launches;  /* number of those launches (= epochs) */
+} kadabra_stats;
+
+/*
+ * Copies an undirected graph, given as symmetric CSR in host memory, to
+ * library-owned device memory and runs the preprocessing that depends on the
+ * graph only: connected components and the vertex-diameter bound (Section
+ * 2.3; Appendix C.1).
+ *   n        number of vertices, 2 <= n < 2^23
+ *   num_arcs number of arcs (twice the edge count), 0 <= num_arcs < 2^31
+ *   row_ptr  host int32[n + 1]; row_ptr[0] = 0, non-decreasing, row_ptr[n] = num_arcs
+ *   col_idx  host int32[num_arcs]; each row strictly ascending, entries in
+ *            [0, n), no self-loops, and (u, v) present iff (v, u) present
+ *   out      receives the handle (NULL on failure)
+ * The caller keeps ownership of its arrays.  Errors: EINVAL (malformed CSR),
+ * ERANGE (n or a degree >= 2^23), ENOMEM, EDEVICE.
+ */
+int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr,
+                         const int32_t *col_idx, kadabra_graph **out);
+
+/*
+ * Sets a run parameter; it applies to the next kadabra_run.
+ *   "check_interval"  N >= 1: the stopping rule is checked after every N
+ *                     samples (Appendix C.2).  Default 1024.  The only key
+ *                     that changes results.
+ *   "team"            0 (auto), 64 (one wavefront per sample) or 256 (one
+ *                     workgroup per sample).  Default 0.
+ *   "slots"           samples in flight, 0 = auto (bounded by device memory).
+ *   "frames"          counter frames F >= 1 the workgroups' increments are
+ *                     spread over, merged at every boundary.  Default 1.
+ *   "overlap"         1: launch the next epoch's samples before the host has
+ *                     read the current check (discarded if it stops); 0: no.
+ *                     Default 1.
+ *   "test_fail_alloc" k >= 1: the k-th device allocation of the next run's
+ *                     buffers fails with ENOMEM (failure-path testing); 0: off.
+ * Errors: EINVAL (unknown key or value out of range).
+ */
+int kadabra_set_param(kadabra_graph *g, const char *key, int64_t value);
+
+/* Reads a parameter set by kadabra_set_param (auto values read as 0). */
+int kadabra_get_param(const kadabra_graph *g, const char *key, int64_t *value);
+
+/*
+ * Selects the HIP stream (a hipStream_t passed as void*) all work of this
+ * handle is issued on; NULL selects the library's own stream.  The stream
+ * must outlive its use by the handle.
+ */
+int kadabra_set_stream(kadabra_graph *g, void *hip_stream);
+
+/*
+ * Runs adaptive sampling to completion (blocking): 0 < eps < 1 additive
+ * error, 0 < delta < 1 failure probability, seed of the counter-based
+ * generator.  omega = ceil(0.5/eps^2 (floor(log2(VD - 2)) + 1 + ln(2/delta)))
+ * and uniform delta_L = delta_U = delta/(4n) (the paper defers both to the
+ * original KADABRA analysis).  Samples are drawn in epochs [B_{k-1}, B_k),
+ * B_k = min(k N, omega); the stopping rule runs on the counters of exactly
+ * samples [0, B_k).  A failed or canceled run leaves the handle usable and no
+ * result readable.  Errors: EINVAL (eps, delta), ERANGE (omega >= 2^31),
+ * ENOMEM, EDEVICE, ECANCELED.
+ */
+int kadabra_run(kadabra_graph *g, double eps, double delta, uint64_t seed);
+
+/*
+ * Reads the last completed run into caller-allocated host memory; any
+ * pointer may be NULL.  scores: double[n], scores[v] = counts[v] / tau
+ * (computed on the device); counts: int32[n]; stats: one kadabra_stats.
+ * Errors: ESTATE (no completed run), EDEVICE.
+ */
+int kadabra_get_scores(const kadabra_graph *g, double *scores, int32_t *counts,
+                       kadabra_stats *stats);
+
+/*
+ * As kadabra_get_scores, but writes device memory on the handle's stream
+ * (scores: device double[n], counts: device int32[n], either may be NULL)
+ * and returns without waiting for the copies.  Errors: ESTATE, EDEVICE.
+ */
+int kadabra_get_scores_device(const kadabra_graph *g, double *scores_dev, int32_t *counts_dev);
+
+/*
+ * Copies the per-boundary decisions of the last run (0: continue, 1: stop
+ * rule met, 2: omega reached) into out[0 .. min(cap, epochs)); *count
+ * receives the number of boundaries.  Errors: ESTATE.
+ */
+int kadabra_get_decisions(const kadabra_graph *g, int8_t *out, int64_t cap, int64_t *count);
+
+/*
+ * Evaluates the stopping-rule functions of Appendix B on the device for
+ * host arrays: f[v], g[v] for b = counts[v] / tau, omega, L = log(1/delta_L),
+ * with the same expression tree and rounding as the stop check inside
+ * kadabra_run (IEEE double, no contraction).  counts: host int32[n];
+ * f, g: host double[n].  Uses the current HIP device; allocates and frees
+ * temporary device memory.  Errors: EINVAL (n < 1, tau < 1, null pointer),
+ * ENOMEM, EDEVICE.
+ */
+int kadabra_eval_stop_fg(int32_t n, const int32_t *counts, int64_t tau, int64_t omega, double L,
+                         double *f, double *g);
+
+/* Asks a run in progress on another thread to stop at its next boundary
+ * (kadabra_run then returns ECANCELED).  Safe to call concurrently. */
+int kadabra_cancel(kadabra_graph *g);
+
+/* Frees the handle and its device memory (NULL is a no-op). */
+void kadabra_destroy_graph(kadabra_graph *g);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *kadabra_last_error(void);
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int kadabra_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KADABRA_H */

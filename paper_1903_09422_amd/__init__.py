@@ -1,0 +1,137 @@
+"""KADABRA adaptive-sampling betweenness centrality on MI355X (gfx950).
+
+Thin Python binding over the C ABI of libkadabra.so (include/kadabra.h):
+argument marshalling only; every step of the sampling path runs in the
+library's HIP kernels.  PyTorch is optional and used only to hand over
+device memory and streams.
+
+    from paper_1903_09422_amd import Graph, graphs
+    g = Graph.from_csr(graphs.rmat(18))
+    g.set_param("check_interval", 16384)
+    g.run(eps=0.01, delta=0.1, seed=1)
+    res = g.result()          # tau, counts, scores, stats, decisions
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from ._lib import EXPORTS, KadabraError, Stats, check, lib  # noqa: F401
+
+__all__ = ["Graph", "RunResult", "KadabraError", "eval_stop_fg", "lib"]
+
+
+@dataclass
+class RunResult:
+    tau: int
+    counts: np.ndarray    # int32[n]
+    scores: np.ndarray    # float64[n], counts / tau, computed on the device
+    stats: dict
+    decisions: np.ndarray  # int8 per boundary: 0 continue, 1 stop rule met, 2 omega
+
+
+class Graph:
+    """A graph resident on the device plus its sampling state (one handle)."""
+
+    def __init__(self, n: int, row_ptr, col):
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        if rp.shape != (n + 1,):
+            raise ValueError("row_ptr must have n + 1 entries")
+        self.n = int(n)
+        h = C.c_void_p()
+        check(lib().kadabra_create_graph(self.n, int(cl.size), rp.ctypes.data, cl.ctypes.data,
+                                         C.byref(h)))
+        self._h = h
+        self._stream_ref = None
+
+    @classmethod
+    def from_csr(cls, csr) -> "Graph":
+        return cls(csr.n, csr.row_ptr, csr.col)
+
+    # -- parameters -------------------------------------------------------
+    def set_param(self, key: str, value: int) -> None:
+        check(lib().kadabra_set_param(self._h, key.encode(), int(value)))
+
+    def get_param(self, key: str) -> int:
+        v = C.c_int64()
+        check(lib().kadabra_get_param(self._h, key.encode(), C.byref(v)))
+        return int(v.value)
+
+    def set_stream(self, stream) -> None:
+        """Issue all work on a HIP stream: a torch.cuda.Stream, a raw handle
+        (int), or None for the library's own stream."""
+        if stream is None:
+            ptr = None
+        elif isinstance(stream, int):
+            ptr = stream
+        else:
+            ptr = int(stream.cuda_stream)
+        self._stream_ref = stream
+        check(lib().kadabra_set_stream(self._h, ptr))
+
+    # -- running ------------------------------------------------------------
+    def run(self, eps: float, delta: float, seed: int) -> None:
+        check(lib().kadabra_run(self._h, float(eps), float(delta), int(seed)))
+
+    def cancel(self) -> None:
+        check(lib().kadabra_cancel(self._h))
+
+    def result(self) -> RunResult:
+        scores = np.empty(self.n, dtype=np.float64)
+        counts = np.empty(self.n, dtype=np.int32)
+        st = Stats()
+        check(lib().kadabra_get_scores(self._h, scores.ctypes.data, counts.ctypes.data,
+                                       C.byref(st)))
+        cnt = C.c_int64()
+        check(lib().kadabra_get_decisions(self._h, None, 0, C.byref(cnt)))
+        dec = np.empty(max(int(cnt.value), 1), dtype=np.int8)
+        check(lib().kadabra_get_decisions(self._h, dec.ctypes.data, dec.size, C.byref(cnt)))
+        return RunResult(tau=int(st.tau), counts=counts, scores=scores, stats=st.as_dict(),
+                         decisions=dec[: int(cnt.value)].copy())
+
+    def stats(self) -> dict:
+        st = Stats()
+        check(lib().kadabra_get_scores(self._h, None, None, C.byref(st)))
+        return st.as_dict()
+
+    def result_device(self, scores=None, counts=None) -> None:
+        """Write scores (float64[n]) and/or counts (int32[n]) into device
+        tensors on the handle's stream (no host round trip)."""
+        sp = None if scores is None else int(scores.data_ptr())
+        cp = None if counts is None else int(counts.data_ptr())
+        for t, dt in ((scores, "float64"), (counts, "int32")):
+            if t is not None and (not t.is_cuda or str(t.dtype) != f"torch.{dt}" or
+                                  t.numel() != self.n or not t.is_contiguous()):
+                raise ValueError(f"expected a contiguous CUDA {dt} tensor of {self.n} elements")
+        check(lib().kadabra_get_scores_device(self._h, sp, cp))
+
+    # -- lifetime -------------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().kadabra_destroy_graph(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def eval_stop_fg(counts, tau: int, omega: int, L: float):
+    """Device evaluation of the stopping-rule functions (f, g) per counter."""
+    c = np.ascontiguousarray(counts, dtype=np.int32)
+    f = np.empty(c.size, dtype=np.float64)
+    g = np.empty(c.size, dtype=np.float64)
+    check(lib().kadabra_eval_stop_fg(c.size, c.ctypes.data, int(tau), int(omega), float(L),
+                                     f.ctypes.data, g.ctypes.data))
+    return f, g

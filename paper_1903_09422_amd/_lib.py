@@ -1,0 +1,90 @@
+"""ctypes declarations of libkadabra.so (the C ABI in include/kadabra.h).
+
+There is no fallback: if the native library is missing, importing the
+binding's functions raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkadabra.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ERANGE, ECANCELED = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE",
+                ESTATE: "ESTATE", ERANGE: "ERANGE", ECANCELED: "ECANCELED"}
+
+# every symbol declared in include/kadabra.h
+EXPORTS = (
+    "kadabra_create_graph", "kadabra_set_param", "kadabra_get_param", "kadabra_set_stream",
+    "kadabra_run", "kadabra_get_scores", "kadabra_get_scores_device", "kadabra_get_decisions",
+    "kadabra_eval_stop_fg", "kadabra_cancel", "kadabra_destroy_graph", "kadabra_last_error",
+    "kadabra_version",
+)
+
+
+class KadabraError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Stats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in (
+        "tau", "omega", "vd_bound", "epochs", "decision", "v_exp", "e_scan", "v_new", "e_pred",
+        "e_bt", "path_interior", "disconnected")] + [
+        ("log_inv_delta", C.c_double), ("ms_sampling", C.c_double), ("ms_total", C.c_double),
+        ("ms_sample_kernels", C.c_double), ("sample_launches", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libkadabra.so and declare its signatures (raises if not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"native library {LIB_PATH} is not built; run "
+                           "`python -c 'import __graft_entry__ as g; g.build()'` first")
+    # One HIP runtime per process: PyTorch ships its own libamdhip64.so.7.  If
+    # torch is importable it is loaded first, and the library's dependency on
+    # the same soname then resolves to torch's copy (otherwise torch would
+    # later load a second runtime that sees no device).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = C.CDLL(LIB_PATH)
+    vp, i64p = C.c_void_p, C.POINTER(C.c_int64)
+    L.kadabra_create_graph.argtypes = [C.c_int32, C.c_int64, vp, vp, C.POINTER(vp)]
+    L.kadabra_set_param.argtypes = [vp, C.c_char_p, C.c_int64]
+    L.kadabra_get_param.argtypes = [vp, C.c_char_p, i64p]
+    L.kadabra_set_stream.argtypes = [vp, vp]
+    L.kadabra_run.argtypes = [vp, C.c_double, C.c_double, C.c_uint64]
+    L.kadabra_get_scores.argtypes = [vp, vp, vp, C.POINTER(Stats)]
+    L.kadabra_get_scores_device.argtypes = [vp, vp, vp]
+    L.kadabra_get_decisions.argtypes = [vp, vp, C.c_int64, i64p]
+    L.kadabra_eval_stop_fg.argtypes = [C.c_int32, vp, C.c_int64, C.c_int64, C.c_double, vp, vp]
+    L.kadabra_cancel.argtypes = [vp]
+    L.kadabra_destroy_graph.argtypes = [vp]
+    L.kadabra_destroy_graph.restype = None
+    L.kadabra_last_error.argtypes = []
+    L.kadabra_last_error.restype = C.c_char_p
+    L.kadabra_version.argtypes = []
+    for name in EXPORTS:
+        if name not in ("kadabra_destroy_graph", "kadabra_last_error"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(status: int) -> None:
+    if status != OK:
+        msg = lib().kadabra_last_error().decode(errors="replace")
+        raise KadabraError(status, msg)

@@ -1,0 +1,781 @@
+// kadabra_kernels.hip -- gfx950 kernels of the KADABRA adaptive-sampling path.
+//
+//   sample_kernel      one team (a wavefront of 64 lanes or a workgroup of 256)
+//                      per sample in flight; persistent over the epoch's sample
+//                      indices, claimed from a counter.  Per sample: pair draw,
+//                      same-component test, balanced bidirectional BFS with
+//                      128-bit path counts, meeting-vertex draw, backtracking
+//                      on CSR + distances, +1 on the interior vertices
+//                      (Section 2.3, Appendix C.1).
+//   merge_check_kernel counters += frames of the epoch (frames zeroed), then
+//                      the FP64 stopping rule f, g <= eps of Appendix B for
+//                      every vertex; one violation flag per epoch.
+//   scores_kernel      b~(v) = c(v) / tau.
+//
+// All path counts and weights are integers, so sums done with atomics in any
+// order give bit-identical results: the output does not depend on the
+// schedule (the determinism of the indexed-frame algorithm, Appendix D).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kadabra_internal.h"
+
+namespace kd {
+
+typedef unsigned __int128 u128;
+
+constexpr int SIGMA_BITS = 104;  // a level is rescaled once its largest count reaches 2^104
+constexpr int WEIGHT_BITS = 40;  // meeting weights are rounded up to at most 2^40
+
+// ---------------------------------------------------------------------------
+// Counter-based random numbers: Philox4x32-10 (Salmon et al., SC'11).
+// Draw j of sample i is the block at counter (i_lo, i_hi, j, 0) under key seed.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t philox_u64(uint64_t seed, uint64_t i, uint32_t j,
+                                               uint64_t *second = nullptr)
+{
+    uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32), c2 = j, c3 = 0u;
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t a0 = 0xD2511F53u * c0, b0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t a1 = 0xCD9E8D57u * c2, b1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = b1 ^ c1 ^ k0;
+        const uint32_t n2 = b0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = a1;
+        c2 = n2;
+        c3 = a0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    if (second) *second = (uint64_t)c2 | ((uint64_t)c3 << 32);
+    return (uint64_t)c0 | ((uint64_t)c1 << 32);
+}
+
+__device__ __forceinline__ u128 to128(Sigma s) { return ((u128)s.hi << 64) | s.lo; }
+
+__device__ __forceinline__ int bitw128(u128 x)
+{
+    const uint64_t hi = (uint64_t)(x >> 64), lo = (uint64_t)x;
+    return hi ? 128 - __clzll((long long)hi) : (lo ? 64 - __clzll((long long)lo) : 0);
+}
+
+// 128-bit add into global memory: low word atomically, carry into the high
+// word.  The final value is the exact sum whatever the order of the adds.
+__device__ __forceinline__ void atomic_add_sigma(Sigma *p, u128 v)
+{
+    const uint64_t lo = (uint64_t)v;
+    const uint64_t old = atomicAdd((unsigned long long *)&p->lo, (unsigned long long)lo);
+    const uint64_t hi = (uint64_t)(v >> 64) + ((old + lo) < old ? 1u : 0u);
+    if (hi) atomicAdd((unsigned long long *)&p->hi, (unsigned long long)hi);
+}
+
+// floor(u * m / 2^64) for 64-bit u and 128-bit m < 2^127
+__device__ __forceinline__ u128 mulhi_64x128(uint64_t u, u128 m)
+{
+    const uint64_t m_lo = (uint64_t)m, m_hi = (uint64_t)(m >> 64);
+    const u128 lo = (u128)u * m_lo;
+    const u128 hi = (u128)u * m_hi;
+    return hi + (lo >> 64);
+}
+
+// Meeting weight: ceil(a * b / 2^sh) for a, b < 2^128 with a result < 2^64.
+struct U256 {
+    u128 hi, lo;
+};
+
+__device__ __forceinline__ U256 mul_128x128(u128 a, u128 b)
+{
+    const uint64_t a0 = (uint64_t)a, a1 = (uint64_t)(a >> 64);
+    const uint64_t b0 = (uint64_t)b, b1 = (uint64_t)(b >> 64);
+    const u128 p00 = (u128)a0 * b0, p01 = (u128)a0 * b1, p10 = (u128)a1 * b0,
+               p11 = (u128)a1 * b1;
+    const u128 mid = (p00 >> 64) + (uint64_t)p01 + (uint64_t)p10;
+    U256 r;
+    r.lo = (u128)(uint64_t)p00 | (mid << 64);
+    r.hi = p11 + (p01 >> 64) + (p10 >> 64) + (mid >> 64);
+    return r;
+}
+
+__device__ __forceinline__ int bitw256(U256 x) { return x.hi ? 128 + bitw128(x.hi) : bitw128(x.lo); }
+
+__device__ __forceinline__ uint64_t ceil_shr256(U256 x, int sh)
+{
+    if (sh == 0) return (uint64_t)x.lo;
+    u128 q;
+    bool rem;
+    if (sh < 128) {
+        q = (x.lo >> sh) | (x.hi << (128 - sh));
+        rem = (x.lo << (128 - sh)) != 0;
+    } else if (sh == 128) {
+        q = x.hi;
+        rem = x.lo != 0;
+    } else {
+        q = x.hi >> (sh - 128);
+        rem = x.lo != 0 || (x.hi << (256 - sh)) != 0;
+    }
+    return (uint64_t)q + (rem ? 1u : 0u);
+}
+
+// ---------------------------------------------------------------------------
+// Team primitives.  A team is the whole workgroup (TEAM == blockDim.x), one
+// wavefront (64) or four (256).  sync() is a workgroup barrier between an
+// agent-scope release and acquire: plain stores reach L2 before any lane's
+// later atomics, and plain loads after it see values written by atomics
+// (performed in L2) before it.
+// ---------------------------------------------------------------------------
+template <int TEAM>
+struct Team {
+    static constexpr int WAVES = TEAM / 64;
+
+    __device__ static __forceinline__ void sync()
+    {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+
+    __device__ static __forceinline__ uint64_t wave_sum(uint64_t v)
+    {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        return v;
+    }
+
+    // sum over the team (result in every lane); red: >= WAVES words of LDS
+    __device__ static uint64_t sum_u64(uint64_t v, uint64_t *red)
+    {
+        v = wave_sum(v);
+        if (WAVES == 1) return v;
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) red[w] = v;
+        __syncthreads();
+        uint64_t t = 0;
+#pragma unroll
+        for (int k = 0; k < WAVES; ++k) t += red[k];
+        __syncthreads();
+        return t;
+    }
+
+    __device__ static u128 sum_u128(u128 v, uint64_t *red)
+    {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint64_t lo = __shfl_xor((uint64_t)v, o, 64);
+            const uint64_t hi = __shfl_xor((uint64_t)(v >> 64), o, 64);
+            v += ((u128)hi << 64) | lo;
+        }
+        if (WAVES == 1) return v;
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            red[2 * w] = (uint64_t)v;
+            red[2 * w + 1] = (uint64_t)(v >> 64);
+        }
+        __syncthreads();
+        u128 t = 0;
+#pragma unroll
+        for (int k = 0; k < WAVES; ++k) t += ((u128)red[2 * k + 1] << 64) | red[2 * k];
+        __syncthreads();
+        return t;
+    }
+
+    __device__ static u128 max_u128(u128 v, uint64_t *red)
+    {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint64_t lo = __shfl_xor((uint64_t)v, o, 64);
+            const uint64_t hi = __shfl_xor((uint64_t)(v >> 64), o, 64);
+            const u128 x = ((u128)hi << 64) | lo;
+            v = x > v ? x : v;
+        }
+        if (WAVES == 1) return v;
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            red[2 * w] = (uint64_t)v;
+            red[2 * w + 1] = (uint64_t)(v >> 64);
+        }
+        __syncthreads();
+        u128 t = 0;
+#pragma unroll
+        for (int k = 0; k < WAVES; ++k) {
+            const u128 x = ((u128)red[2 * k + 1] << 64) | red[2 * k];
+            t = x > t ? x : t;
+        }
+        __syncthreads();
+        return t;
+    }
+
+    __device__ static U256 max_u256(U256 v, uint64_t *red)
+    {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            U256 x;
+            x.lo = ((u128)__shfl_xor((uint64_t)(v.lo >> 64), o, 64) << 64) |
+                   __shfl_xor((uint64_t)v.lo, o, 64);
+            x.hi = ((u128)__shfl_xor((uint64_t)(v.hi >> 64), o, 64) << 64) |
+                   __shfl_xor((uint64_t)v.hi, o, 64);
+            if (x.hi > v.hi || (x.hi == v.hi && x.lo > v.lo)) v = x;
+        }
+        if (WAVES == 1) return v;
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            red[4 * w] = (uint64_t)v.lo;
+            red[4 * w + 1] = (uint64_t)(v.lo >> 64);
+            red[4 * w + 2] = (uint64_t)v.hi;
+            red[4 * w + 3] = (uint64_t)(v.hi >> 64);
+        }
+        __syncthreads();
+        U256 t{0, 0};
+#pragma unroll
+        for (int k = 0; k < WAVES; ++k) {
+            U256 x;
+            x.lo = ((u128)red[4 * k + 1] << 64) | red[4 * k];
+            x.hi = ((u128)red[4 * k + 3] << 64) | red[4 * k + 2];
+            if (x.hi > t.hi || (x.hi == t.hi && x.lo > t.lo)) t = x;
+        }
+        __syncthreads();
+        return t;
+    }
+
+    // exclusive prefix sum of an int over the team (lane order); *total in every lane
+    __device__ static int32_t excl_scan_i32(int32_t v, int32_t *total, uint64_t *red)
+    {
+        const int lw = threadIdx.x & 63;
+        int32_t x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t y = __shfl_up(x, o, 64);
+            if (lw >= o) x += y;
+        }
+        if (WAVES == 1) {
+            *total = __shfl(x, 63, 64);
+            return x - v;
+        }
+        const int w = threadIdx.x >> 6;
+        if (lw == 63) red[w] = (uint64_t)(uint32_t)x;
+        __syncthreads();
+        int32_t off = 0, tot = 0;
+#pragma unroll
+        for (int k = 0; k < WAVES; ++k) {
+            const int32_t t = (int32_t)(uint32_t)red[k];
+            off += (k < w) ? t : 0;
+            tot += t;
+        }
+        __syncthreads();
+        *total = tot;
+        return off + x - v;
+    }
+
+    // exclusive prefix sum of a 128-bit value over the team; *total in every lane
+    __device__ static u128 excl_scan_u128(u128 v, u128 *total, uint64_t *red)
+    {
+        const int lw = threadIdx.x & 63;
+        u128 x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint64_t lo = __shfl_up((uint64_t)x, o, 64);
+            const uint64_t hi = __shfl_up((uint64_t)(x >> 64), o, 64);
+            if (lw >= o) x += ((u128)hi << 64) | lo;
+        }
+        if (WAVES == 1) {
+            *total = ((u128)__shfl((uint64_t)(x >> 64), 63, 64) << 64) | __shfl((uint64_t)x, 63, 64);
+            return x - v;
+        }
+        const int w = threadIdx.x >> 6;
+        if (lw == 63) {
+            red[2 * w] = (uint64_t)x;
+            red[2 * w + 1] = (uint64_t)(x >> 64);
+        }
+        __syncthreads();
+        u128 off = 0, tot = 0;
+#pragma unroll
+        for (int k = 0; k < WAVES; ++k) {
+            const u128 t = ((u128)red[2 * k + 1] << 64) | red[2 * k];
+            off += (k < w) ? t : (u128)0;
+            tot += t;
+        }
+        __syncthreads();
+        *total = tot;
+        return off + x - v;
+    }
+};
+
+// Wave-aggregated append: every active lane with `take` receives a distinct
+// slot index from the LDS counter *cnt (one LDS atomic per wavefront).
+__device__ __forceinline__ int wave_append(bool take, int32_t *cnt)
+{
+    const uint64_t act = __ballot(take);
+    if (act == 0) return -1;
+    const int lw = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)act) - 1;
+    int base = 0;
+    if (lw == leader) base = atomicAdd(cnt, __popcll(act));
+    base = __shfl(base, leader, 64);
+    const uint64_t below = lw ? (act & ((~0ull) >> (64 - lw))) : 0ull;
+    return take ? base + __popcll(below) : -1;
+}
+
+template <int TEAM>
+struct SampleShared {
+    int32_t cu[TEAM];       // frontier chunk: vertex
+    int32_t crs[TEAM];      // frontier chunk: first arc
+    int32_t cpfx[TEAM];     // frontier chunk: exclusive prefix of degrees
+    Sigma cm[TEAM];         // frontier chunk: sigma of the vertex
+    uint64_t red[16];       // team reduction scratch
+    int64_t sample;         // claimed sample index
+    int32_t nnext, nmeet, pick;
+};
+
+// Wave/workgroup-per-sample sampler.  Every lane of the team runs the same
+// control flow; per-sample scalars live in registers (uniform) or LDS.
+template <int TEAM>
+__global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
+{
+    using T = Team<TEAM>;
+    __shared__ SampleShared<TEAM> sm;
+    const int lane = threadIdx.x;
+    const size_t n = (size_t)a.n;
+    const size_t slot = blockIdx.x;
+    uint2 *const dist2 = a.st.dist2 + slot * n;
+    Sigma *const sig0 = a.st.sigma + (2 * slot) * n;
+    Sigma *const sig1 = a.st.sigma + (2 * slot + 1) * n;
+    int32_t *const ball0 = a.st.ball + (2 * slot) * n;
+    int32_t *const ball1 = a.st.ball + (2 * slot + 1) * n;
+    int32_t *const meet = a.st.meet + slot * n;
+    uint64_t *const meetw = a.st.meetw + slot * n;
+    int32_t *const frame =
+        a.frames + ((size_t)a.parity * a.nframes + (blockIdx.x % a.nframes)) * n;
+    const int32_t *const row_ptr = a.row_ptr;
+    const int32_t *const col = a.col;
+
+    // lane-private work counters (summed over the team at exit)
+    uint64_t st_vexp = 0, st_escan = 0, st_vnew = 0, st_epred = 0, st_ebt = 0, st_int = 0,
+             st_disc = 0;
+
+    for (;;) {
+        __syncthreads();
+        if (lane == 0) sm.sample = a.lo + (int64_t)atomicAdd(&a.ctl->claim[a.parity], 1u);
+        T::sync();
+        const int64_t i = sm.sample;
+        if (i >= a.hi) break;
+
+        // -- pair: ordered, s != t, uniform (64-bit multiply-high mapping) --
+        uint64_t u_t;
+        const uint64_t u_s = philox_u64(a.seed, (uint64_t)i, 0u, &u_t);
+        const int32_t s = (int32_t)__umul64hi(u_s, (uint64_t)a.n);
+        int32_t t = (int32_t)__umul64hi(u_t, (uint64_t)(a.n - 1));
+        t += (t >= s) ? 1 : 0;
+        if (a.comp[s] != a.comp[t]) {  // Appendix C.1: no search across components
+            st_disc += (lane == 0);
+            continue;
+        }
+
+        // -- balanced bidirectional BFS with path counts ----------------------
+        if (lane == 0) {
+            dist2[s].x = 1u;
+            dist2[t].y = 1u;
+            sig0[s] = Sigma{1u, 0u};
+            sig1[t] = Sigma{1u, 0u};
+            ball0[0] = s;
+            ball1[0] = t;
+        }
+        // per-side BFS state (uniform across the team; side X selected by value)
+        int32_t lvl0 = 0, lvl1 = 0;
+        int32_t flo0 = 0, flo1 = 0, fhi0 = 1, fhi1 = 1;  // frontier = ball[flo, fhi)
+        int64_t dsum0 = row_ptr[s + 1] - row_ptr[s], dsum1 = row_ptr[t + 1] - row_ptr[t];
+        int X = 0, nN = 0, nM = 0;
+        bool ok = true;
+        T::sync();
+        for (;;) {
+            X = (dsum0 <= dsum1) ? 0 : 1;  // cheaper side; s on ties
+            int32_t *const ballx = X ? ball1 : ball0;
+            Sigma *const sigx = X ? sig1 : sig0;
+            const int32_t lvlx = X ? lvl1 : lvl0;
+            const int32_t flox = X ? flo1 : flo0;
+            const int32_t fhix = X ? fhi1 : fhi0;
+            if (lane == 0) {
+                st_vexp += (uint64_t)(fhix - flox);
+                st_escan += (uint64_t)(X ? dsum1 : dsum0);
+                sm.nnext = 0;
+                sm.nmeet = 0;
+            }
+            const uint32_t enc_new = (uint32_t)lvlx + 2u;  // (dist + 1) of the new level
+            const int32_t base_new = fhix;
+            u128 mass = 0;  // sum of the frontier's sigma: bounds every new count
+            __syncthreads();
+            for (int32_t c0 = flox; c0 < fhix; c0 += TEAM) {
+                const int32_t idx = c0 + lane;
+                int32_t dg = 0;
+                if (idx < fhix) {
+                    const int32_t u = ballx[idx];
+                    const int32_t rs = row_ptr[u];
+                    dg = row_ptr[u + 1] - rs;
+                    const Sigma m = sigx[u];
+                    mass += to128(m);
+                    sm.cu[lane] = u;
+                    sm.crs[lane] = rs;
+                    sm.cm[lane] = m;
+                }
+                int32_t tot;
+                const int32_t ex = T::excl_scan_i32(dg, &tot, sm.red);
+                sm.cpfx[lane] = ex;
+                const int32_t cnt = min(TEAM, fhix - c0);
+                __syncthreads();
+                for (int32_t e = lane; e < tot; e += TEAM) {
+                    // owner of arc e: the last chunk entry whose prefix is <= e
+                    int32_t lo = 0, hi = cnt;
+                    while (hi - lo > 1) {
+                        const int32_t mid = (lo + hi) >> 1;
+                        if (sm.cpfx[mid] <= e) lo = mid; else hi = mid;
+                    }
+                    const int32_t w = col[sm.crs[lo] + (e - sm.cpfx[lo])];
+                    const uint2 d2 = dist2[w];
+                    uint32_t dx = X ? d2.y : d2.x;
+                    bool claimed = false;
+                    if (dx == 0u) {
+                        uint32_t *px = X ? &dist2[w].y : &dist2[w].x;
+                        const uint32_t old = atomicCAS(px, 0u, enc_new);
+                        claimed = (old == 0u);
+                        dx = claimed ? enc_new : old;
+                    }
+                    const int p = wave_append(claimed, &sm.nnext);
+                    if (claimed) ballx[base_new + p] = w;
+                    const bool is_meet = claimed && ((X ? d2.x : d2.y) != 0u);
+                    const int q = wave_append(is_meet, &sm.nmeet);
+                    if (is_meet) meet[q] = w;
+                    if (dx == enc_new) {
+                        atomic_add_sigma(&sigx[w], to128(sm.cm[lo]));
+                        ++st_epred;
+                    }
+                }
+                __syncthreads();
+            }
+            T::sync();
+            nN = sm.nnext;
+            nM = sm.nmeet;
+            if (lane == 0) st_vnew += (uint64_t)nN;
+            if (nN == 0) {  // cannot happen inside one component
+                ok = false;
+                break;
+            }
+            // rescale the new level if its largest count may reach 2^SIGMA_BITS
+            const u128 mass_all = T::sum_u128(mass, sm.red);
+            if (bitw128(mass_all) > SIGMA_BITS) {
+                u128 hm = 0;
+                for (int32_t k = lane; k < nN; k += TEAM) {
+                    const u128 v = to128(sigx[ballx[base_new + k]]);
+                    hm = v > hm ? v : hm;
+                }
+                hm = T::max_u128(hm, sm.red);
+                const int sh = bitw128(hm) - SIGMA_BITS;
+                if (sh > 0) {
+                    const u128 add = ((u128)1 << sh) - 1;
+                    for (int32_t k = lane; k < nN; k += TEAM) {
+                        const int32_t w = ballx[base_new + k];
+                        const u128 v = (to128(sigx[w]) + add) >> sh;
+                        sigx[w] = Sigma{(uint64_t)v, (uint64_t)(v >> 64)};
+                    }
+                }
+                T::sync();
+            }
+            if (nM > 0) break;
+            // advance side X: its frontier becomes the new level
+            uint64_t ds = 0;
+            for (int32_t k = lane; k < nN; k += TEAM) {
+                const int32_t w = ballx[base_new + k];
+                ds += (uint64_t)(row_ptr[w + 1] - row_ptr[w]);
+            }
+            ds = T::sum_u64(ds, sm.red);
+            if (X) {
+                flo1 = fhi1;
+                fhi1 += nN;
+                lvl1 += 1;
+                dsum1 = (int64_t)ds;
+            } else {
+                flo0 = fhi0;
+                fhi0 += nN;
+                lvl0 += 1;
+                dsum0 = (int64_t)ds;
+            }
+        }
+        // the last level built belongs to side X's ball (it is cleared below)
+        const int32_t bend0 = fhi0 + ((X == 0) ? nN : 0);
+        const int32_t bend1 = fhi1 + ((X == 1) ? nN : 0);
+
+        if (ok) {
+            // -- meeting vertex: P(v) = sigma_s(v) sigma_t(v), ascending id ----
+            int32_t v;
+            if (nM == 1) {
+                v = meet[0];
+            } else {
+                U256 pm{0, 0};
+                for (int32_t k = lane; k < nM; k += TEAM) {
+                    const int32_t w = meet[k];
+                    const U256 p = mul_128x128(to128(sig0[w]), to128(sig1[w]));
+                    if (p.hi > pm.hi || (p.hi == pm.hi && p.lo > pm.lo)) pm = p;
+                }
+                pm = T::max_u256(pm, sm.red);
+                const int shp = max(0, bitw256(pm) - WEIGHT_BITS);
+                uint64_t tot = 0;
+                int32_t vmin = a.n, vmax = -1;
+                for (int32_t k = lane; k < nM; k += TEAM) {
+                    const int32_t w = meet[k];
+                    const uint64_t wt = ceil_shr256(mul_128x128(to128(sig0[w]), to128(sig1[w])), shp);
+                    meetw[k] = wt;
+                    tot += wt;
+                    vmin = min(vmin, w);
+                    vmax = max(vmax, w);
+                }
+                tot = T::sum_u64(tot, sm.red);
+                // team min / max of ids through the sum primitive's scratch
+                uint64_t mn = (uint64_t)(uint32_t)(a.n - vmin), mx = (uint64_t)(uint32_t)(vmax + 1);
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    mn = max(mn, (uint64_t)__shfl_xor(mn, o, 64));
+                    mx = max(mx, (uint64_t)__shfl_xor(mx, o, 64));
+                }
+                if (T::WAVES > 1) {
+                    const int wv = lane >> 6;
+                    if ((lane & 63) == 0) {
+                        sm.red[2 * wv] = mn;
+                        sm.red[2 * wv + 1] = mx;
+                    }
+                    __syncthreads();
+                    for (int k = 0; k < T::WAVES; ++k) {
+                        mn = max(mn, sm.red[2 * k]);
+                        mx = max(mx, sm.red[2 * k + 1]);
+                    }
+                    __syncthreads();
+                }
+                T::sync();  // meetw visible to the whole team
+                const uint64_t r = __umul64hi(philox_u64(a.seed, (uint64_t)i, 1u), tot);
+                // smallest id v whose inclusive prefix (ascending ids) exceeds r
+                int32_t lo = a.n - (int32_t)mn, hi = (int32_t)mx - 1;
+                while (lo < hi) {
+                    const int32_t mid = lo + ((hi - lo) >> 1);
+                    uint64_t part = 0;
+                    for (int32_t k = lane; k < nM; k += TEAM) part += (meet[k] <= mid) ? meetw[k] : 0u;
+                    part = T::sum_u64(part, sm.red);
+                    if (part > r) hi = mid; else lo = mid + 1;
+                }
+                v = lo;
+            }
+            const uint2 dv = dist2[v];
+            if (lane == 0 && dv.x > 1u && dv.y > 1u) {
+                atomicAdd(&frame[v], 1);
+                ++st_int;
+            }
+            // -- backtrack towards s (side 0) and t (side 1) -------------------
+            for (int side = 0; side < 2; ++side) {
+                const Sigma *const sg = side ? sig1 : sig0;
+                int32_t x = v;
+                for (;;) {
+                    const uint2 dxx = dist2[x];
+                    const uint32_t ex = side ? dxx.y : dxx.x;
+                    if (ex <= 2u) break;  // x at distance <= 1: the root is next
+                    const uint32_t want = ex - 1u;
+                    const int32_t rs = row_ptr[x], deg = row_ptr[x + 1] - rs;
+                    if (lane == 0) sm.pick = -1;
+                    // lane owns the contiguous arc segment [e0, e1) of x
+                    const int32_t e0 = rs + (int32_t)(((int64_t)deg * lane) / TEAM);
+                    const int32_t e1 = rs + (int32_t)(((int64_t)deg * (lane + 1)) / TEAM);
+                    u128 part = 0;
+                    for (int32_t e = e0; e < e1; ++e) {
+                        const int32_t p = col[e];
+                        const uint2 dp = dist2[p];
+                        if ((side ? dp.y : dp.x) == want) part += to128(sg[p]);
+                    }
+                    u128 tot;
+                    const u128 ex_pre = T::excl_scan_u128(part, &tot, sm.red);
+                    const uint32_t j = 2u * (ex - 1u) + (uint32_t)side;
+                    const u128 r = mulhi_64x128(philox_u64(a.seed, (uint64_t)i, j), tot);
+                    if (part != 0 && ex_pre <= r && r < ex_pre + part) {
+                        u128 acc = ex_pre;
+                        for (int32_t e = e0; e < e1; ++e) {
+                            const int32_t p = col[e];
+                            const uint2 dp = dist2[p];
+                            if ((side ? dp.y : dp.x) != want) continue;
+                            acc += to128(sg[p]);
+                            if (acc > r) {
+                                sm.pick = p;
+                                break;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                    x = sm.pick;
+                    __syncthreads();
+                    if (x < 0) {  // no predecessor found: cannot happen on a BFS level
+                        if (lane == 0) atomicExch(&a.ctl->err, 2);
+                        break;
+                    }
+                    if (lane == 0) {
+                        st_ebt += (uint64_t)deg;
+                        atomicAdd(&frame[x], 1);
+                        ++st_int;
+                    }
+                }
+            }
+        } else if (lane == 0) {
+            atomicExch(&a.ctl->err, 1);
+        }
+
+        // -- clear what this sample touched ----------------------------------
+        for (int32_t k = lane; k < bend0; k += TEAM) {
+            const int32_t w = ball0[k];
+            dist2[w] = make_uint2(0u, 0u);
+            sig0[w] = Sigma{0u, 0u};
+        }
+        for (int32_t k = lane; k < bend1; k += TEAM) {
+            const int32_t w = ball1[k];
+            dist2[w] = make_uint2(0u, 0u);
+            sig1[w] = Sigma{0u, 0u};
+        }
+    }
+
+    // -- work counters -----------------------------------------------------
+    uint64_t *red = sm.red;
+    const uint64_t v0 = T::sum_u64(st_vexp, red), v1 = T::sum_u64(st_escan, red),
+                   v2 = T::sum_u64(st_vnew, red), v3 = T::sum_u64(st_epred, red),
+                   v4 = T::sum_u64(st_ebt, red), v5 = T::sum_u64(st_int, red),
+                   v6 = T::sum_u64(st_disc, red);
+    if (lane == 0) {
+        int64_t *stp = a.ctl->stats[a.parity];
+        if (v0) atomicAdd((unsigned long long *)&stp[ST_VEXP], v0);
+        if (v1) atomicAdd((unsigned long long *)&stp[ST_ESCAN], v1);
+        if (v2) atomicAdd((unsigned long long *)&stp[ST_VNEW], v2);
+        if (v3) atomicAdd((unsigned long long *)&stp[ST_EPRED], v3);
+        if (v4) atomicAdd((unsigned long long *)&stp[ST_EBT], v4);
+        if (v5) atomicAdd((unsigned long long *)&stp[ST_INTERIOR], v5);
+        if (v6) atomicAdd((unsigned long long *)&stp[ST_DISCONN], v6);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Epoch boundary: merge the epoch's frames into the counters (zeroing them)
+// and evaluate the stopping rule of Appendix B on exactly samples [0, tau):
+//   f = (L/tau) (1/3 - w/tau + sqrt((1/3 - w/tau)^2 + 2 b w / L))
+//   g = (L/tau) (1/3 + w/tau + sqrt((1/3 + w/tau)^2 + 2 b w / L))
+// b = c / tau, w = omega, L = log(1/delta_L).  IEEE double in this exact
+// order; the file is compiled without floating-point contraction.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void stop_fg(int32_t c, double t, double w, double L, double *f,
+                                        double *g)
+{
+    const double b = (double)c / t;
+    const double af = 1.0 / 3.0 - w / t;
+    const double ag = 1.0 / 3.0 + w / t;
+    const double q = 2.0 * b * w / L;
+    *f = (L / t) * (af + sqrt(af * af + q));
+    *g = (L / t) * (ag + sqrt(ag * ag + q));
+}
+
+__global__ __launch_bounds__(256) void merge_check_kernel(CheckArgs a)
+{
+    const size_t n = (size_t)a.n;
+    int32_t *const fr = a.frames + (size_t)a.parity * a.nframes * n;
+    const double t = (double)a.tau, w = (double)a.omega;
+    int viol = 0;
+    for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (size_t)gridDim.x * blockDim.x) {
+        int32_t c = a.counts[v];
+        for (int f = 0; f < a.nframes; ++f) {
+            c += fr[(size_t)f * n + v];
+            fr[(size_t)f * n + v] = 0;
+        }
+        a.counts[v] = c;
+        if (a.do_check) {
+            double fv, gv;
+            stop_fg(c, t, w, a.L, &fv, &gv);
+            if (!(fv <= a.eps) || !(gv <= a.eps)) viol = 1;
+        }
+    }
+    if (__syncthreads_or(viol) && threadIdx.x == 0) atomicOr(&a.ctl->viol[a.parity], 1);
+    if (blockIdx.x == 0) {
+        // fold the epoch's work counters into the totals; prepare the next
+        // epoch of the other parity (its claims and flag were last used two
+        // epochs ago, and that flag has been read)
+        if (threadIdx.x < ST_COUNT) {
+            a.ctl->stats_total[threadIdx.x] += a.ctl->stats[a.parity][threadIdx.x];
+            a.ctl->stats[a.parity][threadIdx.x] = 0;
+        }
+        if (threadIdx.x == 0) {
+            a.ctl->claim[a.parity ^ 1] = 0u;
+            a.ctl->viol[a.parity ^ 1] = 0;
+        }
+    }
+}
+
+__global__ void scores_kernel(const int32_t *counts, double *scores, int32_t n, int64_t tau)
+{
+    const double t = (double)tau;
+    for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < (size_t)n;
+         v += (size_t)gridDim.x * blockDim.x)
+        scores[v] = (double)counts[v] / t;
+}
+
+__global__ void eval_fg_kernel(const int32_t *counts, int32_t n, int64_t tau, int64_t omega,
+                               double L, double *f, double *g)
+{
+    for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < (size_t)n;
+         v += (size_t)gridDim.x * blockDim.x)
+        stop_fg(counts[v], (double)tau, (double)omega, L, &f[v], &g[v]);
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, size_t count, uint32_t value)
+{
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
+         k += (size_t)gridDim.x * blockDim.x)
+        p[k] = value;
+}
+
+static unsigned grid_for(size_t count, unsigned block)
+{
+    size_t g = (count + block - 1) / block;
+    if (g > 8192) g = 8192;
+    return g ? (unsigned)g : 1u;
+}
+
+hipError_t launch_sample(int team, int slots, const SampleArgs &a, hipStream_t s)
+{
+    if (team == 64)
+        hipLaunchKernelGGL(sample_kernel<64>, dim3(slots), dim3(64), 0, s, a);
+    else if (team == 256)
+        hipLaunchKernelGGL(sample_kernel<256>, dim3(slots), dim3(256), 0, s, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_check(const CheckArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(merge_check_kernel, dim3(grid_for((size_t)a.n, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_scores(const int32_t *counts, double *scores, int32_t n, int64_t tau,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(scores_kernel, dim3(grid_for((size_t)n, 256)), dim3(256), 0, s, counts,
+                       scores, n, tau);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_fg(const int32_t *counts, int32_t n, int64_t tau, int64_t omega, double L,
+                          double *f, double *g, hipStream_t s)
+{
+    hipLaunchKernelGGL(eval_fg_kernel, dim3(grid_for((size_t)n, 256)), dim3(256), 0, s, counts, n,
+                       tau, omega, L, f, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, size_t count, uint32_t value, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s, p, count,
+                       value);
+    return hipGetLastError();
+}
+
+}  // namespace kd

@@ -1,0 +1,255 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar: bit-exact tau, per-boundary decisions, every counter and every
+algorithm-defined work counter (integer work), for every graph, seed, check
+interval and mapping (team, slots, frames, overlap).
+"""
+import hashlib
+import json
+import os
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_09422_amd import Graph, KadabraError, _lib, eval_stop_fg
+from paper_1903_09422_amd import graphs as G
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+WORK_KEYS = ("v_exp", "e_scan", "v_new", "e_pred", "e_bt", "path_interior", "disconnected")
+
+
+def gpu_run(g, eps, delta, seed, n_check, **params):
+    with Graph.from_csr(g) as dev:
+        dev.set_param("check_interval", n_check)
+        for k, v in params.items():
+            dev.set_param(k, v)
+        dev.run(eps, delta, seed)
+        return dev.result()
+
+
+def assert_same(got, want):
+    assert got.tau == want.tau
+    assert np.array_equal(got.decisions, want.decisions)
+    if not np.array_equal(got.counts, want.counts):
+        bad = np.flatnonzero(got.counts != want.counts)
+        raise AssertionError(f"{bad.size} counters differ, first {bad[:5]}: "
+                             f"gpu {got.counts[bad[:5]]} oracle {want.counts[bad[:5]]}")
+    for k in WORK_KEYS:
+        assert got.stats[k] == want.stats[k], k
+    assert got.stats["omega"] == want.stats["omega"]
+    assert got.stats["vd_bound"] == want.stats["vd"]
+    np.testing.assert_array_equal(got.scores, want.counts / float(want.tau))
+
+
+SMALL = [
+    G.path_graph(2), G.path_graph(40), G.star_graph(25), G.complete_graph(9), G.cycle_graph(31),
+    G.grid_graph(12, 9), G.hypercube(6), G.barbell(7, 6), G.complete_bipartite(5, 8),
+    G.empty_graph(6), G.disjoint_union(G.grid_graph(5, 5), G.star_graph(12), G.path_graph(3)),
+    G.erdos_renyi(700, 7.0, seed=2), G.random_connected(300, 50, seed=4),
+]
+
+
+@pytest.mark.parametrize("team", [64, 256])
+@pytest.mark.parametrize("g", SMALL, ids=lambda g: g.name)
+def test_small_graphs(g, team):
+    print(f"case {g.name} team={team}", flush=True)
+    for seed, n_check in ((1, 64), (9, 333)):
+        want = oracle.run(g, 0.05, 0.1, seed, n_check)
+        got = gpu_run(g, 0.05, 0.1, seed, n_check, team=team)
+        assert_same(got, want)
+
+
+@pytest.mark.parametrize("n_check", [1, 7, 1000, 10**6])
+def test_check_intervals_and_ragged_last_epoch(n_check):
+    g = G.erdos_renyi(400, 5.0, seed=8)
+    print(f"case er400 n_check={n_check}", flush=True)
+    want = oracle.run(g, 0.04, 0.1, 3, n_check)
+    got = gpu_run(g, 0.04, 0.1, 3, n_check)
+    assert_same(got, want)
+
+
+def test_layered_graph_with_huge_sigma():
+    # 17^(d-1) shortest paths: sigma beyond 2^104 forces level rescaling
+    width, layers = 17, 80
+    u, v = [], []
+    for a in range(layers - 1):
+        for i in range(width):
+            for j in range(width):
+                u.append(a * width + i)
+                v.append((a + 1) * width + j)
+    g = G.from_edges(layers * width, u, v, lcc=False)
+    print("case layered 80x17", flush=True)
+    for team in (64, 256):
+        want = oracle.run(g, 0.05, 0.1, 2, 512)
+        got = gpu_run(g, 0.05, 0.1, 2, 512, team=team)
+        assert_same(got, want)
+
+
+def test_er4096_workload():
+    g, eps, delta, n_check = G.workload("er4096")
+    print("case er4096 full", flush=True)
+    want = oracle.run(g, eps, delta, 1, n_check)
+    for team in (64, 256):
+        assert_same(gpu_run(g, eps, delta, 1, n_check, team=team), want)
+
+
+def test_rmat18_workload_full():
+    g, eps, delta, n_check = G.workload("rmat18")
+    print("case rmat18 full (oracle ~5 s)", flush=True)
+    want = oracle.run(g, eps, delta, 1, n_check)
+    got = gpu_run(g, eps, delta, 1, n_check)
+    assert_same(got, want)
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, "oracle_runs.json")) as f:
+        return json.load(f)[name]
+
+
+@pytest.mark.parametrize("name", ["rmat18", "pgrid1024"])
+def test_workload_against_stored_oracle(name):
+    """Full-size runs against the oracle's stored result (written by
+    tests/golden/make_oracle_golden.py, which calls only oracle/)."""
+    ref = _golden(name)
+    g, eps, delta, n_check = G.workload(name)
+    assert g.sha256() == ref["graph_sha256"]
+    print(f"case {name} stored oracle result", flush=True)
+    got = gpu_run(g, eps, delta, ref["seed"], n_check)
+    assert got.tau == ref["tau"]
+    assert got.decisions.tolist() == ref["decisions"]
+    idx = np.asarray(ref["sample_idx"])
+    assert got.counts[idx].tolist() == ref["sample_counts"]
+    assert int(got.counts.sum()) == ref["counts_sum"]
+    assert hashlib.sha256(got.counts.astype("<i4").tobytes()).hexdigest() == ref["counts_sha256"]
+    for k in WORK_KEYS:
+        assert got.stats[k] == ref["stats"][k], k
+
+
+def test_mapping_does_not_change_results():
+    g, eps, delta, n_check = G.workload("rmat18")
+    print("case rmat18 mappings", flush=True)
+    base = gpu_run(g, eps, delta, 5, n_check, team=256)
+    for params in ({"team": 64}, {"team": 256, "slots": 37}, {"team": 64, "slots": 1000},
+                   {"frames": 8}, {"overlap": 0}, {"team": 64, "frames": 3, "overlap": 0}):
+        print("  mapping", params, flush=True)
+        got = gpu_run(g, eps, delta, 5, n_check, **params)
+        assert got.tau == base.tau and np.array_equal(got.counts, base.counts), params
+        for k in WORK_KEYS:
+            assert got.stats[k] == base.stats[k], (params, k)
+
+
+def test_repeated_runs_on_one_handle():
+    g = G.erdos_renyi(1500, 6.0, seed=5)
+    print("case repeated runs", flush=True)
+    with Graph.from_csr(g) as dev:
+        dev.set_param("check_interval", 128)
+        for seed in (1, 2, 1):
+            dev.run(0.03, 0.1, seed)
+            got = dev.result()
+            assert_same(got, oracle.run(g, 0.03, 0.1, seed, 128))
+        dev.set_param("team", 64)  # new buffers, same results
+        dev.run(0.03, 0.1, 2)
+        assert_same(dev.result(), oracle.run(g, 0.03, 0.1, 2, 128))
+
+
+def test_stop_functions_bitwise():
+    """The device f, g (IEEE double, no contraction) equal the oracle's."""
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        omega = int(rng.integers(1, 2**31 - 1))
+        tau = int(rng.integers(1, omega + 1))
+        L = float(np.log(4 * int(rng.integers(2, 2**23)) / rng.uniform(0.001, 0.999)))
+        counts = rng.integers(0, tau + 1, size=5000).astype(np.int32)
+        f, g = eval_stop_fg(counts, tau, omega, L)
+        for k in range(0, 5000, 97):
+            fo, go = oracle.fg(int(counts[k]), tau, omega, L)
+            assert f[k] == fo and g[k] == go, (counts[k], tau, omega, L)
+
+
+def test_errors_and_state():
+    g = G.grid_graph(6, 6)
+    with Graph.from_csr(g) as dev:
+        with pytest.raises(KadabraError) as e:
+            dev.result()
+        assert e.value.status == _lib.ESTATE
+        for eps, delta in ((0.0, 0.1), (1.5, 0.1), (0.1, 0.0), (0.1, 1.0)):
+            with pytest.raises(KadabraError) as e:
+                dev.run(eps, delta, 1)
+            assert e.value.status == _lib.EINVAL
+        with pytest.raises(KadabraError) as e:
+            dev.run(1e-6, 0.1, 1)  # omega beyond int32 counters
+        assert e.value.status == _lib.ERANGE
+        with pytest.raises(KadabraError) as e:
+            dev.set_param("nonsense", 1)
+        assert e.value.status == _lib.EINVAL
+        with pytest.raises(KadabraError):
+            dev.set_param("team", 128)
+        # forced allocation failure: ENOMEM, no result, handle still usable
+        dev.set_param("test_fail_alloc", 3)
+        with pytest.raises(KadabraError) as e:
+            dev.run(0.1, 0.1, 1)
+        assert e.value.status == _lib.ENOMEM
+        with pytest.raises(KadabraError) as e:
+            dev.result()
+        assert e.value.status == _lib.ESTATE
+        dev.run(0.1, 0.1, 1)
+        assert_same(dev.result(), oracle.run(g, 0.1, 0.1, 1, 1024))
+
+
+def test_cancel_from_another_thread():
+    g, _, _, _ = G.workload("pgrid1024")
+    print("case cancel", flush=True)
+    with Graph.from_csr(g) as dev:
+        dev.set_param("check_interval", 64)  # many boundaries
+        th = threading.Timer(0.3, dev.cancel)
+        th.start()
+        t0 = time.time()
+        with pytest.raises(KadabraError) as e:
+            dev.run(0.002, 0.1, 1)  # omega ~ 1.4M samples: far longer than 0.3 s
+        th.join()
+        assert e.value.status == _lib.ECANCELED
+        assert time.time() - t0 < 30
+        with pytest.raises(KadabraError):
+            dev.result()
+
+
+def test_torch_stream_and_device_outputs():
+    torch = pytest.importorskip("torch")
+    g = G.erdos_renyi(900, 6.0, seed=6)
+    want = oracle.run(g, 0.05, 0.1, 4, 256)
+    stream = torch.cuda.Stream()
+    with Graph.from_csr(g) as dev:
+        dev.set_stream(stream)
+        dev.set_param("check_interval", 256)
+        dev.run(0.05, 0.1, 4)
+        scores = torch.empty(g.n, dtype=torch.float64, device="cuda")
+        counts = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        dev.result_device(scores=scores, counts=counts)
+        stream.synchronize()
+        assert np.array_equal(counts.cpu().numpy(), want.counts)
+        assert np.array_equal(scores.cpu().numpy(), want.counts / float(want.tau))
+
+
+def test_philox_against_rocrand():
+    """The oracle's Philox4x32-10 equals rocRAND's (an independent
+    implementation), which also fixes the device path through parity."""
+    import ctypes as C
+    L = C.CDLL("librocrand.so")
+    gen = C.c_void_p()
+    assert L.rocrand_create_generator_host_blocking(C.byref(gen), 401) == 0  # PHILOX4_32_10
+    seed = 0x0123456789ABCDEF
+    assert L.rocrand_set_seed(gen, C.c_ulonglong(seed)) == 0
+    out = np.zeros(4 * 64, dtype=np.uint32)
+    rc = L.rocrand_generate(gen, out.ctypes.data_as(C.c_void_p), C.c_size_t(out.size))
+    L.rocrand_destroy_generator(gen)
+    if rc != 0:
+        pytest.skip(f"rocRAND host generator unavailable (status {rc})")
+    blocks = {tuple(oracle.philox4x32_10([k, 0, 0, 0], [seed & 0xFFFFFFFF, seed >> 32]))
+              for k in range(64)}
+    got = {tuple(int(x) for x in out[4 * k: 4 * k + 4]) for k in range(64)}
+    assert got == blocks
