@@ -25,13 +25,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
-# Algorithmic bytes per unit of work counted by the sampler:
+# Algorithmic bytes per unit of work counted by the sampler (a lower bound:
+# what any implementation of the method must read per unit):
 BYTES_PER = {
-    "v_exp": 28,          # frontier vertex: row_ptr pair 8 + sigma 16 + ball entry 4
-    "e_scan": 12,         # scanned arc: col 4 + dist word 8
-    "v_new": 40,          # new vertex: claim 4 + ball 4 + row_ptr pair 8 + clear dist 8 + sigma 16
-    "e_pred": 16,         # predecessor arc: 128-bit sigma add
-    "e_bt": 28,           # backtracking arc: col 4 + dist 8 + sigma 16
+    "v_exp": 28,          # expanded frontier vertex: row_ptr pair 8 + sigma 16 + list entry 4
+    "e_scan": 12,         # scanned arc: column index 4 + the neighbour's distance pair 8
+    "e_bt": 12,           # arc scanned when backtracking: column index 4 + distance pair 8
     "path_interior": 4,   # counter increment
 }
 
@@ -66,11 +65,24 @@ def main() -> int:
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--frames", type=int, default=1)
     ap.add_argument("--overlap", type=int, default=1)
+    ap.add_argument("--probe-min", type=int, default=-1)
     ap.add_argument("--cpu-repeats", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per sampler launch from rocprofv3 counters, if measured")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES device-to-device once (profiler calibration) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+
+        src = torch.ones(args.calibrate_copy // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": src.numel() * 4}))
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the sampling "
               "path here is single-device; see DESIGN.md for how it would shard.", file=sys.stderr)
@@ -87,6 +99,7 @@ def main() -> int:
     dev.set_param("slots", args.slots)
     dev.set_param("frames", args.frames)
     dev.set_param("overlap", args.overlap)
+    dev.set_param("probe_min", args.probe_min)
     stream = torch.cuda.Stream()
     dev.set_stream(stream)
     scores = torch.empty(g.n, dtype=torch.float64, device="cuda")
@@ -139,7 +152,8 @@ def main() -> int:
             "tau": int(st["tau"]),
             "omega": int(st["omega"]),
             "mapping": {"team": dev.get_param("last_team"), "slots": dev.get_param("last_slots"),
-                        "frames": args.frames, "overlap": args.overlap},
+                        "frames": args.frames, "overlap": args.overlap,
+                        "probe_min": args.probe_min},
         },
         "traversed_edges_per_s": escan / dt,
         "query_latency_ms": {"p50": float(np.percentile(lat, 50)),

@@ -52,10 +52,8 @@ typedef struct {
     int64_t decision;      /* 1: stopping rule met; 2: omega reached */
     /* algorithmic work, summed over the tau samples (independent of mapping) */
     int64_t v_exp;         /* frontier vertices expanded */
-    int64_t e_scan;        /* arcs scanned by expansions: traversed edges */
-    int64_t v_new;         /* vertices newly reached */
-    int64_t e_pred;        /* predecessor arcs summed into sigma */
-    int64_t e_bt;          /* arcs scanned while backtracking */
+    int64_t e_scan;        /* sum of the expanded frontiers' degrees: traversed edges */
+    int64_t e_bt;          /* sum of the degrees of the path vertices backtracked from */
     int64_t path_interior; /* counter increments */
     int64_t disconnected;  /* samples with s, t in different components */
     double log_inv_delta;  /* L = log(1/delta_L) = log(4 n / delta) */
@@ -96,6 +94,10 @@ int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr,
  *   "overlap"         1: launch the next epoch's samples before the host has
  *                     read the current check (discarded if it stops); 0: no.
  *                     Default 1.
+ *   "probe_min"       expansions scanning at least this many arcs first look
+ *                     for the meeting set without materialising the new level
+ *                     (-1: every expansion if the mean degree is at least 6,
+ *                     none otherwise).  Default -1.
  *   "test_fail_alloc" k >= 1: the k-th device allocation of the next run's
  *                     buffers fails with ENOMEM (failure-path testing); 0: off.
  * Errors: EINVAL (unknown key or value out of range).

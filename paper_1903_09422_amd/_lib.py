@@ -32,8 +32,8 @@ class KadabraError(RuntimeError):
 
 class Stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
-        "tau", "omega", "vd_bound", "epochs", "decision", "v_exp", "e_scan", "v_new", "e_pred",
-        "e_bt", "path_interior", "disconnected")] + [
+        "tau", "omega", "vd_bound", "epochs", "decision", "v_exp", "e_scan", "e_bt",
+        "path_interior", "disconnected")] + [
         ("log_inv_delta", C.c_double), ("ms_sampling", C.c_double), ("ms_total", C.c_double),
         ("ms_sample_kernels", C.c_double), ("sample_launches", C.c_int64)]
 

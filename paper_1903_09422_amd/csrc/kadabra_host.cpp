@@ -91,6 +91,7 @@ struct kadabra_graph {
     int frames = 1;
     int overlap = 1;
     int64_t fail_alloc = 0;  // test hook: the fail_alloc-th run-buffer allocation fails
+    int64_t probe_min = -1;  // meeting-probe threshold in arcs; -1 = auto
 
     // run buffers (kept across runs; grown when needed)
     int rb_team = 0;
@@ -129,8 +130,8 @@ struct kadabra_graph {
 
     void release_run_buffers()
     {
-        dev_free(st.dist2);
-        dev_free(st.sigma);
+        dev_free(st.rec);
+        dev_free(st.loff);
         dev_free(st.ball);
         dev_free(st.meet);
         dev_free(st.meetw);
@@ -151,10 +152,10 @@ struct kadabra_graph {
 namespace {
 
 // Bytes of per-slot sampling state for a graph of n vertices.
-size_t slot_bytes(int32_t n)
+size_t slot_bytes(int32_t n, int32_t lcap)
 {
-    return (size_t)n * (sizeof(uint2) + 2 * sizeof(kd::Sigma) + 2 * sizeof(int32_t) +
-                        sizeof(int32_t) + sizeof(uint64_t));
+    return (size_t)n * (sizeof(kd::VRec) + 2 * sizeof(int32_t) + sizeof(int32_t) + sizeof(uint64_t)) +
+           2 * (size_t)lcap * sizeof(int32_t);
 }
 
 int validate_csr(int32_t n, int64_t num_arcs, const int32_t *row_ptr, const int32_t *col,
@@ -264,8 +265,10 @@ int ensure_run_buffers(kadabra_graph *g, int team, int64_t slots, int frames)
     g->release_run_buffers();
     const size_t n = (size_t)g->n;
     const size_t S = (size_t)slots;
-    HIP_OR_FAIL(dev_alloc((void **)&g->st.dist2, S * n * sizeof(uint2), &g->fail_alloc));
-    HIP_OR_FAIL(dev_alloc((void **)&g->st.sigma, S * 2 * n * sizeof(kd::Sigma), &g->fail_alloc));
+    const int32_t lcap = g->vd + 2;  // a side reaches at most diameter <= VD - 1 levels
+    HIP_OR_FAIL(dev_alloc((void **)&g->st.rec, S * n * sizeof(kd::VRec), &g->fail_alloc));
+    HIP_OR_FAIL(dev_alloc((void **)&g->st.loff, S * 2 * (size_t)lcap * sizeof(int32_t), &g->fail_alloc));
+    g->st.lcap = lcap;
     HIP_OR_FAIL(dev_alloc((void **)&g->st.ball, S * 2 * n * sizeof(int32_t), &g->fail_alloc));
     HIP_OR_FAIL(dev_alloc((void **)&g->st.meet, S * n * sizeof(int32_t), &g->fail_alloc));
     HIP_OR_FAIL(dev_alloc((void **)&g->st.meetw, S * n * sizeof(uint64_t), &g->fail_alloc));
@@ -290,7 +293,7 @@ void choose_mapping(const kadabra_graph *g, int *team, int64_t *slots)
         sl = (int64_t)std::max(g->num_cu, 1) * per_cu;
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0) {
-            const int64_t fit = (int64_t)((free_b / 2) / slot_bytes(g->n));
+            const int64_t fit = (int64_t)((free_b / 2) / slot_bytes(g->n, g->vd + 2));
             sl = std::min(sl, std::max<int64_t>(fit, 1));
         }
     }
@@ -320,8 +323,8 @@ int run_impl(kadabra_graph *g, double eps, double delta, uint64_t seed)
     hipStream_t s = g->stream;
     const size_t n = (size_t)g->n;
     if (g->state_dirty) {
-        HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)g->st.dist2, (size_t)slots * n * 2, 0u, s));
-        HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)g->st.sigma, (size_t)slots * n * 8, 0u, s));
+        HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)g->st.rec, (size_t)slots * n * (sizeof(kd::VRec) / 4),
+                                        0u, s));
         g->state_dirty = false;
     }
     HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)g->d_counts, n, 0u, s));
@@ -335,6 +338,11 @@ int run_impl(kadabra_graph *g, double eps, double delta, uint64_t seed)
     sa.n = g->n;
     sa.nframes = g->frames;
     sa.seed = seed;
+    // auto: probe every expansion on graphs of mean degree >= 6 (small
+    // diameter: the level that meets is the large one); never on sparse,
+    // high-diameter graphs, where only the last of many levels meets
+    sa.probe_min = (g->probe_min >= 0) ? g->probe_min
+                                       : ((g->arcs >= 6 * (int64_t)g->n) ? 0 : ((int64_t)1 << 62));
     sa.frames = g->d_frames;
     sa.ctl = g->d_ctl;
     sa.st = g->st;
@@ -363,6 +371,7 @@ int run_impl(kadabra_graph *g, double eps, double delta, uint64_t seed)
             sa.lo = lo;
             sa.hi = hi;
             sa.parity = par;
+            sa.gate = -1;  // the host knows the previous boundary did not stop
             HIP_OR_FAIL(hipEventRecord(g->ev_ks[par], s));
             HIP_OR_FAIL(kd::launch_sample(team, (int)slots, sa, s));
             HIP_OR_FAIL(hipEventRecord(g->ev_ke[par], s));
@@ -380,6 +389,7 @@ int run_impl(kadabra_graph *g, double eps, double delta, uint64_t seed)
             sa.lo = hi;
             sa.hi = std::min<int64_t>((k + 1) * N, omega);
             sa.parity = par ^ 1;
+            sa.gate = par;  // exits at once if this boundary's check stops the run
             HIP_OR_FAIL(hipEventRecord(g->ev_ks[par ^ 1], s));
             HIP_OR_FAIL(kd::launch_sample(team, (int)slots, sa, s));
             HIP_OR_FAIL(hipEventRecord(g->ev_ke[par ^ 1], s));
@@ -506,6 +516,9 @@ int kadabra_set_param(kadabra_graph *g, const char *key, int64_t value)
     } else if (!strcmp(key, "overlap")) {
         if (value != 0 && value != 1) return fail(KADABRA_EINVAL, "overlap must be 0 or 1");
         g->overlap = (int)value;
+    } else if (!strcmp(key, "probe_min")) {
+        if (value < -1) return fail(KADABRA_EINVAL, "probe_min must be >= -1");
+        g->probe_min = value;
     } else if (!strcmp(key, "test_fail_alloc")) {
         if (value < 0) return fail(KADABRA_EINVAL, "test_fail_alloc must be >= 0");
         g->fail_alloc = value;
@@ -524,6 +537,7 @@ int kadabra_get_param(const kadabra_graph *g, const char *key, int64_t *value)
     else if (!strcmp(key, "slots")) *value = g->slots;
     else if (!strcmp(key, "frames")) *value = g->frames;
     else if (!strcmp(key, "overlap")) *value = g->overlap;
+    else if (!strcmp(key, "probe_min")) *value = g->probe_min;
     else if (!strcmp(key, "vd_bound")) *value = g->vd;
     else if (!strcmp(key, "components")) *value = g->ncomp;
     else if (!strcmp(key, "max_degree")) *value = g->max_deg;
@@ -570,8 +584,6 @@ int kadabra_get_scores(const kadabra_graph *g, double *scores, int32_t *counts, 
         stats->decision = g->decision;
         stats->v_exp = g->work[kd::ST_VEXP];
         stats->e_scan = g->work[kd::ST_ESCAN];
-        stats->v_new = g->work[kd::ST_VNEW];
-        stats->e_pred = g->work[kd::ST_EPRED];
         stats->e_bt = g->work[kd::ST_EBT];
         stats->path_interior = g->work[kd::ST_INTERIOR];
         stats->disconnected = g->work[kd::ST_DISCONN];
@@ -636,6 +648,20 @@ int kadabra_eval_stop_fg(int32_t n, const int32_t *counts, int64_t tau, int64_t 
     cleanup();
     return KADABRA_OK;
 }
+
+#ifdef KADABRA_PHASE_TIMERS
+// Phase-timer builds only: cycles per sampler phase summed over all launches
+// of the last run (0 pair, 1 expansion, 2 level bookkeeping, 3 meeting draw,
+// 4 backtracking, 5 clearing).
+int kadabra_debug_phase_cycles(const kadabra_graph *g, int64_t *out8)
+{
+    if (!g || !g->d_ctl || !out8) return fail(KADABRA_EINVAL, "bad argument");
+    kd::Control ctl;
+    HIP_OR_FAIL(hipMemcpy(&ctl, g->d_ctl, sizeof ctl, hipMemcpyDeviceToHost));
+    for (int k = 0; k < 8; ++k) out8[k] = ctl.phase_cycles[k];
+    return KADABRA_OK;
+}
+#endif
 
 int kadabra_cancel(kadabra_graph *g)
 {

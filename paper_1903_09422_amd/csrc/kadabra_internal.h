@@ -17,9 +17,7 @@ struct Sigma {
 enum StatIdx {
     ST_VEXP = 0,   // frontier vertices expanded
     ST_ESCAN,      // arcs scanned by expansions
-    ST_VNEW,       // vertices newly reached
-    ST_EPRED,      // predecessor arcs summed into sigma
-    ST_EBT,        // arcs scanned while backtracking
+    ST_EBT,        // arcs scanned while backtracking (sum of the path vertices' degrees)
     ST_INTERIOR,   // counter increments
     ST_DISCONN,    // samples with endpoints in different components
     ST_COUNT
@@ -33,16 +31,27 @@ struct Control {
     int32_t pad;
     int64_t stats[2][ST_COUNT];      // work counters of the epoch in flight, by parity
     int64_t stats_total[ST_COUNT];   // work counters of merged epochs
+    int64_t phase_cycles[8];         // per-phase cycles (phase-timer builds only)
 };
 
-// Per-slot sampling state: every array holds `n` entries per slot.  Between
-// samples dist2 and sigma are all zero (each sample clears what it touched).
+// Per-vertex sampling record of one slot: both sides' distance and path
+// count in one 64-byte line, so a visited vertex costs one line.
+struct alignas(64) VRec {
+    uint32_t dist[2];  // dist_s + 1, dist_t + 1; 0 = not reached
+    uint32_t pad0[2];
+    Sigma sig[2];      // sigma_s, sigma_t
+    uint64_t pad1[2];
+};
+
+// Per-slot sampling state.  Between samples every record is all zero (each
+// sample clears the records it touched).
 struct SlotState {
-    uint2 *dist2;     // [slots][n] {dist_s + 1, dist_t + 1}; 0 = not reached
-    Sigma *sigma;     // [slots][2][n] sigma_s, sigma_t
+    VRec *rec;        // [slots][n]
     int32_t *ball;    // [slots][2][n] vertices reached by each side, BFS order
     int32_t *meet;    // [slots][n] meeting set
-    uint64_t *meetw;  // [slots][n] meeting weights
+    uint64_t *meetw;  // [slots][n] meeting weights (when the set exceeds LDS)
+    int32_t *loff;    // [slots][2][lcap] start of each BFS level in ball
+    int32_t lcap;     // entries per side (diameter bound + 2)
 };
 
 struct SampleArgs {
@@ -54,6 +63,9 @@ struct SampleArgs {
     uint64_t seed;
     int64_t lo, hi;   // sample indices of this epoch: [lo, hi)
     int32_t parity;   // epoch parity (selects claim counter, frames, stats)
+    int64_t probe_min;  // expansions of at least this many arcs probe for the meeting first
+    int32_t gate;     // -1, or the parity of the previous boundary: if its check
+                      // found no violation the run has stopped and this launch exits
     int32_t *frames;  // [2][nframes][n]
     Control *ctl;
     SlotState st;

@@ -61,14 +61,27 @@ __device__ __forceinline__ int bitw128(u128 x)
     return hi ? 128 - __clzll((long long)hi) : (lo ? 64 - __clzll((long long)lo) : 0);
 }
 
+// Workgroup-scope atomics on a sample's private state.
+__device__ __forceinline__ uint64_t wg_add_u64(uint64_t *p, uint64_t v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ uint32_t wg_cas_u32(uint32_t *p, uint32_t expected, uint32_t desired)
+{
+    __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+    return expected;  // the value found: == the argument iff the swap happened
+}
+
 // 128-bit add into global memory: low word atomically, carry into the high
 // word.  The final value is the exact sum whatever the order of the adds.
 __device__ __forceinline__ void atomic_add_sigma(Sigma *p, u128 v)
 {
     const uint64_t lo = (uint64_t)v;
-    const uint64_t old = atomicAdd((unsigned long long *)&p->lo, (unsigned long long)lo);
+    const uint64_t old = wg_add_u64(&p->lo, lo);
     const uint64_t hi = (uint64_t)(v >> 64) + ((old + lo) < old ? 1u : 0u);
-    if (hi) atomicAdd((unsigned long long *)&p->hi, (unsigned long long)hi);
+    if (hi) wg_add_u64(&p->hi, hi);
 }
 
 // floor(u * m / 2^64) for 64-bit u and 128-bit m < 2^127
@@ -120,21 +133,16 @@ __device__ __forceinline__ uint64_t ceil_shr256(U256 x, int sh)
 
 // ---------------------------------------------------------------------------
 // Team primitives.  A team is the whole workgroup (TEAM == blockDim.x), one
-// wavefront (64) or four (256).  sync() is a workgroup barrier between an
-// agent-scope release and acquire: plain stores reach L2 before any lane's
-// later atomics, and plain loads after it see values written by atomics
-// (performed in L2) before it.
+// wavefront (64) or four (256).  A sample's state is touched by its own
+// workgroup only, so workgroup scope is all the ordering it needs: sync() is
+// the workgroup barrier, and the state's atomics are workgroup-scope (they
+// resolve in the XCD's own L2 instead of travelling to memory).
 // ---------------------------------------------------------------------------
 template <int TEAM>
 struct Team {
     static constexpr int WAVES = TEAM / 64;
 
-    __device__ static __forceinline__ void sync()
-    {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
+    __device__ static __forceinline__ void sync() { __syncthreads(); }
 
     __device__ static __forceinline__ uint64_t wave_sum(uint64_t v)
     {
@@ -316,16 +324,67 @@ __device__ __forceinline__ int wave_append(bool take, int32_t *cnt)
     return take ? base + __popcll(below) : -1;
 }
 
+// Optional per-phase cycle counters (compile with -DKADABRA_PHASE_TIMERS):
+// lane 0 of each team adds the shader-clock cycles of each phase of a sample
+// into Control::phase_cycles.  Off in the library build.
+#ifdef KADABRA_PHASE_TIMERS
+#define PHASE_BEGIN() uint64_t ph_t0_ = __builtin_readcyclecounter()
+#define PHASE_MARK(k)                                                   \
+    do {                                                                \
+        const uint64_t ph_t1_ = __builtin_readcyclecounter();           \
+        if (threadIdx.x == 0) ph_acc[k] += ph_t1_ - ph_t0_;             \
+        ph_t0_ = ph_t1_;                                                \
+    } while (0)
+#else
+#define PHASE_BEGIN() (void)0
+#define PHASE_MARK(k) (void)0
+#endif
+
+// LDS staging capacity for the meeting set and for backtracking candidates
+template <int TEAM>
+struct Cap {
+    static constexpr int STAGE = (TEAM == 64) ? 256 : 1024;
+};
+
 template <int TEAM>
 struct SampleShared {
-    int32_t cu[TEAM];       // frontier chunk: vertex
-    int32_t crs[TEAM];      // frontier chunk: first arc
-    int32_t cpfx[TEAM];     // frontier chunk: exclusive prefix of degrees
-    Sigma cm[TEAM];         // frontier chunk: sigma of the vertex
-    uint64_t red[16];       // team reduction scratch
-    int64_t sample;         // claimed sample index
-    int32_t nnext, nmeet, pick;
+    int32_t cu[TEAM];                 // frontier chunk: vertex
+    int32_t crs[TEAM];                // frontier chunk: first arc
+    int32_t cpfx[TEAM];               // frontier chunk: exclusive prefix of degrees
+    Sigma cm[TEAM];                   // frontier chunk: sigma of the vertex
+    int32_t sv[Cap<TEAM>::STAGE];     // staged meeting vertices / candidates
+    Sigma sw[Cap<TEAM>::STAGE];       // their weights
+    uint64_t red[16];                 // team reduction scratch
+    int64_t sample;                   // claimed sample index
+    int32_t nnext, nmeet, pick, ncand;
 };
+
+// lower bound of `key` in the sorted row col[0, len): true if present
+__device__ __forceinline__ bool row_contains(const int32_t *row, int32_t len, int32_t key)
+{
+    int32_t lo = 0, hi = len;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (row[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo < len && row[lo] == key;
+}
+
+// Among staged (id, weight) pairs sv/sw[0, cnt), the lane holding the
+// smallest id whose inclusive prefix (ascending id) exceeds r writes it to
+// *pick.  Ids are distinct; total weight > r.
+template <int TEAM>
+__device__ __forceinline__ void pick_by_id_prefix(const int32_t *sv, const Sigma *sw, int32_t cnt,
+                                                  u128 r, int32_t *pick)
+{
+    for (int32_t k = threadIdx.x; k < cnt; k += TEAM) {
+        const int32_t c = sv[k];
+        u128 pre = 0;
+        for (int32_t j = 0; j < cnt; ++j) pre += (sv[j] <= c) ? to128(sw[j]) : (u128)0;
+        const u128 wk = to128(sw[k]);
+        if (pre > r && pre - wk <= r) *pick = c;
+    }
+}
 
 // Wave/workgroup-per-sample sampler.  Every lane of the team runs the same
 // control flow; per-sample scalars live in registers (uniform) or LDS.
@@ -333,25 +392,32 @@ template <int TEAM>
 __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
 {
     using T = Team<TEAM>;
+    constexpr int STAGE = Cap<TEAM>::STAGE;
     __shared__ SampleShared<TEAM> sm;
     const int lane = threadIdx.x;
     const size_t n = (size_t)a.n;
     const size_t slot = blockIdx.x;
-    uint2 *const dist2 = a.st.dist2 + slot * n;
-    Sigma *const sig0 = a.st.sigma + (2 * slot) * n;
-    Sigma *const sig1 = a.st.sigma + (2 * slot + 1) * n;
+    VRec *const rec = a.st.rec + slot * n;
     int32_t *const ball0 = a.st.ball + (2 * slot) * n;
     int32_t *const ball1 = a.st.ball + (2 * slot + 1) * n;
     int32_t *const meet = a.st.meet + slot * n;
     uint64_t *const meetw = a.st.meetw + slot * n;
+    int32_t *const loff0 = a.st.loff + (2 * slot) * (size_t)a.st.lcap;
+    int32_t *const loff1 = loff0 + a.st.lcap;
     int32_t *const frame =
         a.frames + ((size_t)a.parity * a.nframes + (blockIdx.x % a.nframes)) * n;
     const int32_t *const row_ptr = a.row_ptr;
     const int32_t *const col = a.col;
 
+    // launched before the host has read the previous boundary's check: stream
+    // order has already run that check, so its flag decides
+    if (a.gate >= 0 && a.ctl->viol[a.gate] == 0) return;
+
+#ifdef KADABRA_PHASE_TIMERS
+    uint64_t ph_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#endif
     // lane-private work counters (summed over the team at exit)
-    uint64_t st_vexp = 0, st_escan = 0, st_vnew = 0, st_epred = 0, st_ebt = 0, st_int = 0,
-             st_disc = 0;
+    uint64_t st_vexp = 0, st_escan = 0, st_ebt = 0, st_int = 0, st_disc = 0;
 
     for (;;) {
         __syncthreads();
@@ -359,6 +425,7 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
         T::sync();
         const int64_t i = sm.sample;
         if (i >= a.hi) break;
+        PHASE_BEGIN();
 
         // -- pair: ordered, s != t, uniform (64-bit multiply-high mapping) --
         uint64_t u_t;
@@ -370,33 +437,54 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
             st_disc += (lane == 0);
             continue;
         }
+        PHASE_MARK(0);
 
         // -- balanced bidirectional BFS with path counts ----------------------
         if (lane == 0) {
-            dist2[s].x = 1u;
-            dist2[t].y = 1u;
-            sig0[s] = Sigma{1u, 0u};
-            sig1[t] = Sigma{1u, 0u};
+            rec[s].dist[0] = 1u;
+            rec[t].dist[1] = 1u;
+            rec[s].sig[0] = Sigma{1u, 0u};
+            rec[t].sig[1] = Sigma{1u, 0u};
             ball0[0] = s;
             ball1[0] = t;
+            loff0[0] = 0;
+            loff0[1] = 1;
+            loff1[0] = 0;
+            loff1[1] = 1;
         }
         // per-side BFS state (uniform across the team; side X selected by value)
         int32_t lvl0 = 0, lvl1 = 0;
         int32_t flo0 = 0, flo1 = 0, fhi0 = 1, fhi1 = 1;  // frontier = ball[flo, fhi)
         int64_t dsum0 = row_ptr[s + 1] - row_ptr[s], dsum1 = row_ptr[t + 1] - row_ptr[t];
+        u128 fmass0 = 1, fmass1 = 1;  // sum of the frontier's sigma
         int X = 0, nN = 0, nM = 0;
-        bool ok = true;
+        bool ok = true, retry = false;
         T::sync();
         for (;;) {
             X = (dsum0 <= dsum1) ? 0 : 1;  // cheaper side; s on ties
             int32_t *const ballx = X ? ball1 : ball0;
-            Sigma *const sigx = X ? sig1 : sig0;
             const int32_t lvlx = X ? lvl1 : lvl0;
             const int32_t flox = X ? flo1 : flo0;
             const int32_t fhix = X ? fhi1 : fhi0;
+            const int64_t dsx = X ? dsum1 : dsum0;
+            if (lvlx + 3 > a.st.lcap) {  // more levels than the diameter bound allows
+                ok = false;
+                nN = 0;
+                break;
+            }
+            // Meeting probe: on a large expansion, first claim only the new
+            // vertices the other side has already reached.  If there are any,
+            // they are the whole meeting set and the rest of the level is never
+            // needed (sigma of a meeting vertex is the same sum either way);
+            // otherwise the level is expanded in full.  The probe cannot skip a
+            // rescaling: it runs only when the frontier's mass is below 2^104.
+            const bool probe = !retry && dsx >= a.probe_min &&
+                               bitw128(X ? fmass1 : fmass0) <= SIGMA_BITS;
             if (lane == 0) {
-                st_vexp += (uint64_t)(fhix - flox);
-                st_escan += (uint64_t)(X ? dsum1 : dsum0);
+                if (!retry) {
+                    st_vexp += (uint64_t)(fhix - flox);
+                    st_escan += (uint64_t)dsx;
+                }
                 sm.nnext = 0;
                 sm.nmeet = 0;
             }
@@ -411,7 +499,7 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                     const int32_t u = ballx[idx];
                     const int32_t rs = row_ptr[u];
                     dg = row_ptr[u + 1] - rs;
-                    const Sigma m = sigx[u];
+                    const Sigma m = rec[u].sig[X];
                     mass += to128(m);
                     sm.cu[lane] = u;
                     sm.crs[lane] = rs;
@@ -430,31 +518,34 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                         if (sm.cpfx[mid] <= e) lo = mid; else hi = mid;
                     }
                     const int32_t w = col[sm.crs[lo] + (e - sm.cpfx[lo])];
-                    const uint2 d2 = dist2[w];
+                    VRec *const rw = &rec[w];
+                    const uint2 d2 = *reinterpret_cast<const uint2 *>(rw->dist);
                     uint32_t dx = X ? d2.y : d2.x;
+                    const uint32_t dy = X ? d2.x : d2.y;
                     bool claimed = false;
-                    if (dx == 0u) {
-                        uint32_t *px = X ? &dist2[w].y : &dist2[w].x;
-                        const uint32_t old = atomicCAS(px, 0u, enc_new);
+                    if (dx == 0u && (!probe || dy != 0u)) {
+                        const uint32_t old = wg_cas_u32(&rw->dist[X], 0u, enc_new);
                         claimed = (old == 0u);
                         dx = claimed ? enc_new : old;
                     }
                     const int p = wave_append(claimed, &sm.nnext);
                     if (claimed) ballx[base_new + p] = w;
-                    const bool is_meet = claimed && ((X ? d2.x : d2.y) != 0u);
+                    const bool is_meet = claimed && dy != 0u;
                     const int q = wave_append(is_meet, &sm.nmeet);
                     if (is_meet) meet[q] = w;
-                    if (dx == enc_new) {
-                        atomic_add_sigma(&sigx[w], to128(sm.cm[lo]));
-                        ++st_epred;
-                    }
+                    if (dx == enc_new) atomic_add_sigma(&rw->sig[X], to128(sm.cm[lo]));
                 }
                 __syncthreads();
             }
             T::sync();
+            PHASE_MARK(1);
             nN = sm.nnext;
             nM = sm.nmeet;
-            if (lane == 0) st_vnew += (uint64_t)nN;
+            if (probe && nM == 0) {  // no meeting on this level: expand it in full
+                retry = true;
+                continue;
+            }
+            retry = false;
             if (nN == 0) {  // cannot happen inside one component
                 ok = false;
                 break;
@@ -464,7 +555,7 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
             if (bitw128(mass_all) > SIGMA_BITS) {
                 u128 hm = 0;
                 for (int32_t k = lane; k < nN; k += TEAM) {
-                    const u128 v = to128(sigx[ballx[base_new + k]]);
+                    const u128 v = to128(rec[ballx[base_new + k]].sig[X]);
                     hm = v > hm ? v : hm;
                 }
                 hm = T::max_u128(hm, sm.red);
@@ -473,31 +564,39 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                     const u128 add = ((u128)1 << sh) - 1;
                     for (int32_t k = lane; k < nN; k += TEAM) {
                         const int32_t w = ballx[base_new + k];
-                        const u128 v = (to128(sigx[w]) + add) >> sh;
-                        sigx[w] = Sigma{(uint64_t)v, (uint64_t)(v >> 64)};
+                        const u128 v = (to128(rec[w].sig[X]) + add) >> sh;
+                        rec[w].sig[X] = Sigma{(uint64_t)v, (uint64_t)(v >> 64)};
                     }
                 }
                 T::sync();
             }
+            PHASE_MARK(2);
             if (nM > 0) break;
             // advance side X: its frontier becomes the new level
             uint64_t ds = 0;
+            u128 ms = 0;
             for (int32_t k = lane; k < nN; k += TEAM) {
                 const int32_t w = ballx[base_new + k];
                 ds += (uint64_t)(row_ptr[w + 1] - row_ptr[w]);
+                ms += to128(rec[w].sig[X]);
             }
             ds = T::sum_u64(ds, sm.red);
+            ms = T::sum_u128(ms, sm.red);
+            if (lane == 0) (X ? loff1 : loff0)[lvlx + 2] = fhix + nN;
             if (X) {
                 flo1 = fhi1;
                 fhi1 += nN;
                 lvl1 += 1;
                 dsum1 = (int64_t)ds;
+                fmass1 = ms;
             } else {
                 flo0 = fhi0;
                 fhi0 += nN;
                 lvl0 += 1;
                 dsum0 = (int64_t)ds;
+                fmass0 = ms;
             }
+            PHASE_MARK(2);
         }
         // the last level built belongs to side X's ball (it is cleared below)
         const int32_t bend0 = fhi0 + ((X == 0) ? nN : 0);
@@ -509,10 +608,11 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
             if (nM == 1) {
                 v = meet[0];
             } else {
+                const bool staged = nM <= STAGE;
                 U256 pm{0, 0};
                 for (int32_t k = lane; k < nM; k += TEAM) {
                     const int32_t w = meet[k];
-                    const U256 p = mul_128x128(to128(sig0[w]), to128(sig1[w]));
+                    const U256 p = mul_128x128(to128(rec[w].sig[0]), to128(rec[w].sig[1]));
                     if (p.hi > pm.hi || (p.hi == pm.hi && p.lo > pm.lo)) pm = p;
                 }
                 pm = T::max_u256(pm, sm.red);
@@ -521,14 +621,20 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                 int32_t vmin = a.n, vmax = -1;
                 for (int32_t k = lane; k < nM; k += TEAM) {
                     const int32_t w = meet[k];
-                    const uint64_t wt = ceil_shr256(mul_128x128(to128(sig0[w]), to128(sig1[w])), shp);
-                    meetw[k] = wt;
+                    const uint64_t wt =
+                        ceil_shr256(mul_128x128(to128(rec[w].sig[0]), to128(rec[w].sig[1])), shp);
+                    if (staged) {
+                        sm.sv[k] = w;
+                        sm.sw[k] = Sigma{wt, 0u};
+                    } else {
+                        meetw[k] = wt;
+                    }
                     tot += wt;
                     vmin = min(vmin, w);
                     vmax = max(vmax, w);
                 }
                 tot = T::sum_u64(tot, sm.red);
-                // team min / max of ids through the sum primitive's scratch
+                // team min / max of the ids (as maxima of n - id and id + 1)
                 uint64_t mn = (uint64_t)(uint32_t)(a.n - vmin), mx = (uint64_t)(uint32_t)(vmax + 1);
 #pragma unroll
                 for (int o = 32; o > 0; o >>= 1) {
@@ -548,58 +654,106 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                     }
                     __syncthreads();
                 }
-                T::sync();  // meetw visible to the whole team
+                T::sync();  // staged weights visible to the whole team
                 const uint64_t r = __umul64hi(philox_u64(a.seed, (uint64_t)i, 1u), tot);
                 // smallest id v whose inclusive prefix (ascending ids) exceeds r
                 int32_t lo = a.n - (int32_t)mn, hi = (int32_t)mx - 1;
                 while (lo < hi) {
                     const int32_t mid = lo + ((hi - lo) >> 1);
                     uint64_t part = 0;
-                    for (int32_t k = lane; k < nM; k += TEAM) part += (meet[k] <= mid) ? meetw[k] : 0u;
+                    if (staged) {
+                        for (int32_t k = lane; k < nM; k += TEAM)
+                            part += (sm.sv[k] <= mid) ? sm.sw[k].lo : 0u;
+                    } else {
+                        for (int32_t k = lane; k < nM; k += TEAM)
+                            part += (meet[k] <= mid) ? meetw[k] : 0u;
+                    }
                     part = T::sum_u64(part, sm.red);
                     if (part > r) hi = mid; else lo = mid + 1;
                 }
                 v = lo;
             }
-            const uint2 dv = dist2[v];
+            PHASE_MARK(3);
+            const uint2 dv = *reinterpret_cast<const uint2 *>(rec[v].dist);
             if (lane == 0 && dv.x > 1u && dv.y > 1u) {
                 atomicAdd(&frame[v], 1);
                 ++st_int;
             }
             // -- backtrack towards s (side 0) and t (side 1) -------------------
-            for (int side = 0; side < 2; ++side) {
-                const Sigma *const sg = side ? sig1 : sig0;
+            for (int side = 0; side < 2 && ok; ++side) {
+                const int32_t *const balls = side ? ball1 : ball0;
+                const int32_t *const loffs = side ? loff1 : loff0;
                 int32_t x = v;
                 for (;;) {
-                    const uint2 dxx = dist2[x];
-                    const uint32_t ex = side ? dxx.y : dxx.x;
+                    const uint32_t ex = rec[x].dist[side];
                     if (ex <= 2u) break;  // x at distance <= 1: the root is next
                     const uint32_t want = ex - 1u;
                     const int32_t rs = row_ptr[x], deg = row_ptr[x + 1] - rs;
-                    if (lane == 0) sm.pick = -1;
-                    // lane owns the contiguous arc segment [e0, e1) of x
-                    const int32_t e0 = rs + (int32_t)(((int64_t)deg * lane) / TEAM);
-                    const int32_t e1 = rs + (int32_t)(((int64_t)deg * (lane + 1)) / TEAM);
-                    u128 part = 0;
-                    for (int32_t e = e0; e < e1; ++e) {
-                        const int32_t p = col[e];
-                        const uint2 dp = dist2[p];
-                        if ((side ? dp.y : dp.x) == want) part += to128(sg[p]);
-                    }
-                    u128 tot;
-                    const u128 ex_pre = T::excl_scan_u128(part, &tot, sm.red);
+                    // predecessors = x's neighbours on level dist(x) - 1 of this side
+                    const int32_t llo = loffs[ex - 2u], lhi = loffs[ex - 1u];
                     const uint32_t j = 2u * (ex - 1u) + (uint32_t)side;
-                    const u128 r = mulhi_64x128(philox_u64(a.seed, (uint64_t)i, j), tot);
-                    if (part != 0 && ex_pre <= r && r < ex_pre + part) {
-                        u128 acc = ex_pre;
-                        for (int32_t e = e0; e < e1; ++e) {
+                    const uint64_t U = philox_u64(a.seed, (uint64_t)i, j);
+                    if (lane == 0) {
+                        sm.pick = -1;
+                        sm.ncand = 0;
+                    }
+                    __syncthreads();
+                    bool done = false;
+                    if ((int64_t)(lhi - llo) * 24 < (int64_t)deg) {
+                        // short level, long row: probe each level vertex in x's
+                        // sorted row; stage the candidates with their counts
+                        for (int32_t k = llo + lane; k < lhi; k += TEAM) {
+                            const int32_t p = balls[k];
+                            const bool hit = row_contains(col + rs, deg, p);
+                            const int at = wave_append(hit, &sm.ncand);
+                            if (hit && at < STAGE) {
+                                sm.sv[at] = p;
+                                sm.sw[at] = rec[p].sig[side];
+                            }
+                        }
+                        __syncthreads();
+                        const int32_t nc = sm.ncand;
+                        if (nc <= STAGE) {
+                            u128 part = 0;
+                            for (int32_t k = lane; k < nc; k += TEAM) part += to128(sm.sw[k]);
+                            const u128 tot = T::sum_u128(part, sm.red);
+                            const u128 r = mulhi_64x128(U, tot);
+                            pick_by_id_prefix<TEAM>(sm.sv, sm.sw, nc, r, &sm.pick);
+                            done = true;
+                        }
+                    }
+                    if (!done) {
+                        // scan x's row: lane owns the contiguous arc segment [e0, e1)
+                        const int32_t e0 = rs + (int32_t)(((int64_t)deg * lane) / TEAM);
+                        const int32_t e1 = rs + (int32_t)(((int64_t)deg * (lane + 1)) / TEAM);
+                        u128 part = 0;
+                        int32_t e = e0;
+                        for (; e + 4 <= e1; e += 4) {  // four independent loads in flight
+                            const int32_t p0 = col[e], p1 = col[e + 1], p2 = col[e + 2], p3 = col[e + 3];
+                            const uint32_t d0 = rec[p0].dist[side], d1 = rec[p1].dist[side];
+                            const uint32_t d2 = rec[p2].dist[side], d3 = rec[p3].dist[side];
+                            if (d0 == want) part += to128(rec[p0].sig[side]);
+                            if (d1 == want) part += to128(rec[p1].sig[side]);
+                            if (d2 == want) part += to128(rec[p2].sig[side]);
+                            if (d3 == want) part += to128(rec[p3].sig[side]);
+                        }
+                        for (; e < e1; ++e) {
                             const int32_t p = col[e];
-                            const uint2 dp = dist2[p];
-                            if ((side ? dp.y : dp.x) != want) continue;
-                            acc += to128(sg[p]);
-                            if (acc > r) {
-                                sm.pick = p;
-                                break;
+                            if (rec[p].dist[side] == want) part += to128(rec[p].sig[side]);
+                        }
+                        u128 tot;
+                        const u128 ex_pre = T::excl_scan_u128(part, &tot, sm.red);
+                        const u128 r = mulhi_64x128(U, tot);
+                        if (part != 0 && ex_pre <= r && r < ex_pre + part) {
+                            u128 acc = ex_pre;
+                            for (int32_t q = e0; q < e1; ++q) {
+                                const int32_t p = col[q];
+                                if (rec[p].dist[side] != want) continue;
+                                acc += to128(rec[p].sig[side]);
+                                if (acc > r) {
+                                    sm.pick = p;
+                                    break;
+                                }
                             }
                         }
                     }
@@ -608,6 +762,7 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                     __syncthreads();
                     if (x < 0) {  // no predecessor found: cannot happen on a BFS level
                         if (lane == 0) atomicExch(&a.ctl->err, 2);
+                        ok = false;
                         break;
                     }
                     if (lane == 0) {
@@ -620,32 +775,36 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
         } else if (lane == 0) {
             atomicExch(&a.ctl->err, 1);
         }
+        PHASE_MARK(4);
 
         // -- clear what this sample touched ----------------------------------
-        for (int32_t k = lane; k < bend0; k += TEAM) {
-            const int32_t w = ball0[k];
-            dist2[w] = make_uint2(0u, 0u);
-            sig0[w] = Sigma{0u, 0u};
+        const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+        for (int32_t k = lane; k < bend0 + bend1; k += TEAM) {
+            const int32_t w = (k < bend0) ? ball0[k] : ball1[k - bend0];
+            uint4 *const r4 = reinterpret_cast<uint4 *>(&rec[w]);
+            // the whole 64-byte record: a full-sector write needs no read
+            r4[0] = z4;
+            r4[1] = z4;
+            r4[2] = z4;
+            r4[3] = z4;
         }
-        for (int32_t k = lane; k < bend1; k += TEAM) {
-            const int32_t w = ball1[k];
-            dist2[w] = make_uint2(0u, 0u);
-            sig1[w] = Sigma{0u, 0u};
-        }
+        PHASE_MARK(5);
     }
 
+#ifdef KADABRA_PHASE_TIMERS
+    if (lane == 0)
+        for (int k = 0; k < 8; ++k)
+            if (ph_acc[k]) atomicAdd((unsigned long long *)&a.ctl->phase_cycles[k], ph_acc[k]);
+#endif
     // -- work counters -----------------------------------------------------
     uint64_t *red = sm.red;
     const uint64_t v0 = T::sum_u64(st_vexp, red), v1 = T::sum_u64(st_escan, red),
-                   v2 = T::sum_u64(st_vnew, red), v3 = T::sum_u64(st_epred, red),
                    v4 = T::sum_u64(st_ebt, red), v5 = T::sum_u64(st_int, red),
                    v6 = T::sum_u64(st_disc, red);
     if (lane == 0) {
         int64_t *stp = a.ctl->stats[a.parity];
         if (v0) atomicAdd((unsigned long long *)&stp[ST_VEXP], v0);
         if (v1) atomicAdd((unsigned long long *)&stp[ST_ESCAN], v1);
-        if (v2) atomicAdd((unsigned long long *)&stp[ST_VNEW], v2);
-        if (v3) atomicAdd((unsigned long long *)&stp[ST_EPRED], v3);
         if (v4) atomicAdd((unsigned long long *)&stp[ST_EBT], v4);
         if (v5) atomicAdd((unsigned long long *)&stp[ST_INTERIOR], v5);
         if (v6) atomicAdd((unsigned long long *)&stp[ST_DISCONN], v6);
