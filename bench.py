@@ -68,11 +68,18 @@ def main() -> int:
     ap.add_argument("--probe-min", type=int, default=-1)
     ap.add_argument("--cpu-repeats", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
-                    help="HBM bytes per sampler launch from rocprofv3 counters, if measured")
+    ap.add_argument("--traffic-json", default=None,
+                    help="HBM bytes per sampler launch from rocprofv3 counters (default: "
+                         "profiles/sample_kernel_<workload>_traffic.json)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES device-to-device once (profiler calibration) and exit")
+    ap.add_argument("--ingest-pmc", metavar="DIR",
+                    help="read rocprofv3 outputs under DIR (kernel trace and FETCH_SIZE / "
+                         "WRITE_SIZE passes of this bench and of --calibrate-copy) and write the "
+                         "sampler's traffic summary under profiles/, then exit")
     args = ap.parse_args()
+    if args.ingest_pmc:
+        return ingest_pmc(args.ingest_pmc, args.workload)
     if args.calibrate_copy:
         import torch
 
@@ -129,11 +136,14 @@ def main() -> int:
 
     achieved = kern_bytes / (kern_ms * 1e-3) / 1e9  # GB/s over the sampler launches
     traffic = None
-    if os.path.exists(args.traffic_json):
-        with open(args.traffic_json) as f:
+    tj_path = args.traffic_json or os.path.join(ROOT, "profiles",
+                                                f"sample_kernel_{args.workload}_traffic.json")
+    if os.path.exists(tj_path):
+        with open(tj_path) as f:
             tj = json.load(f)
         if tj.get("workload") == args.workload and tj.get("kernel_source_sha") == _kernel_sha():
             traffic = tj.get("hbm_bytes_per_launch")
+    traffic_gbs = None if traffic is None else traffic / (kern_ms / max(launches, 1) * 1e-3) / 1e9
     out = {
         "metric": "samples/s (KADABRA adaptive sampling, eps=0.01)",
         "value": samples / dt,
@@ -166,6 +176,7 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "traffic_gbs": traffic_gbs,
             "avg_launch_ms": kern_ms / max(launches, 1),
             "algorithmic_bytes_per_launch": kern_bytes / max(launches, 1),
         },
@@ -174,6 +185,85 @@ def main() -> int:
         out["cpu_baseline"] = cpu_baseline(g, eps, delta, args.seed, n_check, args.cpu_repeats)
     dev.close()
     print(json.dumps(out))
+    return 0
+
+
+COPY_BYTES = 1 << 30
+PMC_CMDS = {
+    "trace": "rocprofv3 --kernel-trace --stats -f csv -d DIR/ktrace -o bench -- "
+             "python3 bench.py --workload {w} --steps 5 --warmup 1 --no-cpu",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d DIR/pmc_FETCH_SIZE -o bench -- "
+             "python3 bench.py --workload {w} --steps 2 --warmup 0 --no-cpu",
+    "write": "rocprofv3 --pmc WRITE_SIZE -f csv -d DIR/pmc_WRITE_SIZE -o bench -- "
+             "python3 bench.py --workload {w} --steps 2 --warmup 0 --no-cpu",
+    "copy_fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d DIR/pmc_copy_FETCH_SIZE -o copy -- "
+                  "python3 bench.py --calibrate-copy 1073741824",
+    "copy_write": "rocprofv3 --pmc WRITE_SIZE -f csv -d DIR/pmc_copy_WRITE_SIZE -o copy -- "
+                  "python3 bench.py --calibrate-copy 1073741824",
+}
+
+
+def ingest_pmc(d: str, workload: str) -> int:
+    """Turn rocprofv3 CSVs into the committed summary of the sampler kernel:
+    average duration, and HBM bytes per launch = FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch) each scaled by the factor that maps the same counter,
+    read on a plain 1 GiB device copy, onto the bytes that copy moves."""
+    import csv
+
+    def rows(path):
+        with open(path) as f:
+            return list(csv.DictReader(f))
+
+    def kib(sub, prefix, name):
+        out = []
+        for r in rows(os.path.join(d, sub, f"{prefix}_counter_collection.csv")):
+            if name in r["Kernel_Name"]:
+                out.append(float(r["Counter_Value"]))
+        return out
+
+    fetch_factor = COPY_BYTES / (kib("pmc_copy_FETCH_SIZE", "copy", "copyBuffer")[0] * 1024)
+    write_factor = COPY_BYTES / (kib("pmc_copy_WRITE_SIZE", "copy", "copyBuffer")[0] * 1024)
+    # launches that sampled (the gated speculative launch exits at once)
+    fetch = [x for x in kib("pmc_FETCH_SIZE", "bench", "sample_kernel") if x > 1024]
+    write = [x for x in kib("pmc_WRITE_SIZE", "bench", "sample_kernel") if x > 1024]
+    hbm = (np.mean(fetch) * 1024 * fetch_factor) + (np.mean(write) * 1024 * write_factor)
+    stats = rows(os.path.join(d, "ktrace", "bench_kernel_stats.csv"))
+    trace = rows(os.path.join(d, "ktrace", "bench_kernel_trace.csv"))
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6 for r in trace
+            if "sample_kernel" in r["Kernel_Name"]]
+    full = [x for x in durs if x > 0.05 * max(durs)]
+    summary = {
+        "kernel": "sample_kernel", "workload": workload, "kernel_source_sha": _kernel_sha(),
+        "hbm_bytes_per_launch": hbm,
+        "fetch_kib_per_launch": float(np.mean(fetch)), "write_kib_per_launch": float(np.mean(write)),
+        "fetch_factor": fetch_factor, "write_factor": write_factor,
+        "avg_launch_ms_sampling_launches": float(np.mean(full)),
+        "commands": {k: v.format(w=workload) for k, v in PMC_CMDS.items()},
+    }
+    base = os.path.join(ROOT, "profiles", f"sample_kernel_{workload}")
+    with open(base + "_traffic.json", "w") as f:
+        json.dump(summary, f, indent=1)
+        f.write("\n")
+    with open(base + ".md", "w") as f:
+        f.write(f"# sample_kernel on {workload}: rocprofv3 summary\n\n")
+        f.write("Commands (run from the repository root; DIR = output folder):\n\n")
+        for k, v in summary["commands"].items():
+            f.write(f"- {k}: `{v}`\n")
+        f.write("\n## Kernel statistics (--kernel-trace --stats)\n\n")
+        f.write("| kernel | calls | total ms | average ms | % |\n|---|---|---|---|---|\n")
+        for r in stats:
+            f.write(f"| {r['Name'][:60]} | {r['Calls']} | {float(r['TotalDurationNs']) * 1e-6:.3f} | "
+                    f"{float(r['AverageNs']) * 1e-6:.3f} | {float(r['Percentage']):.1f} |\n")
+        f.write(f"\nSampling launches of the sampler (speculative launches that exit at once "
+                f"excluded): {len(full)}, average {np.mean(full):.3f} ms.\n")
+        f.write("\n## HBM traffic (--pmc, one pass per counter)\n\n")
+        f.write(f"- FETCH_SIZE per sampling launch: {np.mean(fetch):.0f} KiB; copy calibration "
+                f"factor {fetch_factor:.3f} (a 1 GiB device copy reads "
+                f"{COPY_BYTES / fetch_factor / 1024:.0f} KiB)\n")
+        f.write(f"- WRITE_SIZE per sampling launch: {np.mean(write):.0f} KiB; calibration factor "
+                f"{write_factor:.3f}\n")
+        f.write(f"- HBM bytes per launch: {hbm / 1e9:.3f} GB\n")
+    print(json.dumps(summary))
     return 0
 
 

@@ -94,10 +94,10 @@ int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr,
  *   "overlap"         1: launch the next epoch's samples before the host has
  *                     read the current check (discarded if it stops); 0: no.
  *                     Default 1.
- *   "probe_min"       expansions scanning at least this many arcs first look
- *                     for the meeting set without materialising the new level
- *                     (-1: every expansion if the mean degree is at least 6,
- *                     none otherwise).  Default -1.
+ *   "probe_min"       k >= 0: expansions scanning at least k arcs first look
+ *                     for the meeting set without materialising the new level;
+ *                     -1 (default): when the product of the two frontiers'
+ *                     degree sums reaches four times the arc count.
  *   "test_fail_alloc" k >= 1: the k-th device allocation of the next run's
  *                     buffers fails with ENOMEM (failure-path testing); 0: off.
  * Errors: EINVAL (unknown key or value out of range).

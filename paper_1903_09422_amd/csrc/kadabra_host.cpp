@@ -130,7 +130,8 @@ struct kadabra_graph {
 
     void release_run_buffers()
     {
-        dev_free(st.rec);
+        dev_free(st.code);
+        dev_free(st.sigma);
         dev_free(st.loff);
         dev_free(st.ball);
         dev_free(st.meet);
@@ -152,9 +153,12 @@ struct kadabra_graph {
 namespace {
 
 // Bytes of per-slot sampling state for a graph of n vertices.
+int32_t code_stride(int32_t n) { return ((n + 7) / 8 + 15) / 16 * 16; }
+
 size_t slot_bytes(int32_t n, int32_t lcap)
 {
-    return (size_t)n * (sizeof(kd::VRec) + 2 * sizeof(int32_t) + sizeof(int32_t) + sizeof(uint64_t)) +
+    return (size_t)code_stride(n) * 4 +
+           (size_t)n * (2 * sizeof(kd::Sigma) + 2 * sizeof(int32_t) + sizeof(int32_t) + sizeof(uint64_t)) +
            2 * (size_t)lcap * sizeof(int32_t);
 }
 
@@ -266,9 +270,12 @@ int ensure_run_buffers(kadabra_graph *g, int team, int64_t slots, int frames)
     const size_t n = (size_t)g->n;
     const size_t S = (size_t)slots;
     const int32_t lcap = g->vd + 2;  // a side reaches at most diameter <= VD - 1 levels
-    HIP_OR_FAIL(dev_alloc((void **)&g->st.rec, S * n * sizeof(kd::VRec), &g->fail_alloc));
+    const int32_t cstride = code_stride(g->n);
+    HIP_OR_FAIL(dev_alloc((void **)&g->st.code, S * (size_t)cstride * sizeof(uint32_t), &g->fail_alloc));
+    HIP_OR_FAIL(dev_alloc((void **)&g->st.sigma, S * 2 * n * sizeof(kd::Sigma), &g->fail_alloc));
     HIP_OR_FAIL(dev_alloc((void **)&g->st.loff, S * 2 * (size_t)lcap * sizeof(int32_t), &g->fail_alloc));
     g->st.lcap = lcap;
+    g->st.code_stride = cstride;
     HIP_OR_FAIL(dev_alloc((void **)&g->st.ball, S * 2 * n * sizeof(int32_t), &g->fail_alloc));
     HIP_OR_FAIL(dev_alloc((void **)&g->st.meet, S * n * sizeof(int32_t), &g->fail_alloc));
     HIP_OR_FAIL(dev_alloc((void **)&g->st.meetw, S * n * sizeof(uint64_t), &g->fail_alloc));
@@ -323,8 +330,8 @@ int run_impl(kadabra_graph *g, double eps, double delta, uint64_t seed)
     hipStream_t s = g->stream;
     const size_t n = (size_t)g->n;
     if (g->state_dirty) {
-        HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)g->st.rec, (size_t)slots * n * (sizeof(kd::VRec) / 4),
-                                        0u, s));
+        HIP_OR_FAIL(kd::launch_fill_u32(g->st.code, (size_t)slots * g->st.code_stride, 0u, s));
+        HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)g->st.sigma, (size_t)slots * n * 8, 0u, s));
         g->state_dirty = false;
     }
     HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)g->d_counts, n, 0u, s));
@@ -338,11 +345,8 @@ int run_impl(kadabra_graph *g, double eps, double delta, uint64_t seed)
     sa.n = g->n;
     sa.nframes = g->frames;
     sa.seed = seed;
-    // auto: probe every expansion on graphs of mean degree >= 6 (small
-    // diameter: the level that meets is the large one); never on sparse,
-    // high-diameter graphs, where only the last of many levels meets
-    sa.probe_min = (g->probe_min >= 0) ? g->probe_min
-                                       : ((g->arcs >= 6 * (int64_t)g->n) ? 0 : ((int64_t)1 << 62));
+    sa.probe_min = g->probe_min;
+    sa.num_arcs = g->arcs;
     sa.frames = g->d_frames;
     sa.ctl = g->d_ctl;
     sa.st = g->st;

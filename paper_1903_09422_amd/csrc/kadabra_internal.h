@@ -34,24 +34,17 @@ struct Control {
     int64_t phase_cycles[8];         // per-phase cycles (phase-timer builds only)
 };
 
-// Per-vertex sampling record of one slot: both sides' distance and path
-// count in one 64-byte line, so a visited vertex costs one line.
-struct alignas(64) VRec {
-    uint32_t dist[2];  // dist_s + 1, dist_t + 1; 0 = not reached
-    uint32_t pad0[2];
-    Sigma sig[2];      // sigma_s, sigma_t
-    uint64_t pad1[2];
-};
-
-// Per-slot sampling state.  Between samples every record is all zero (each
-// sample clears the records it touched).
+// Per-slot sampling state.  Between samples every code word and every sigma
+// is zero (each sample clears what it touched).
 struct SlotState {
-    VRec *rec;        // [slots][n]
-    int32_t *ball;    // [slots][2][n] vertices reached by each side, BFS order
-    int32_t *meet;    // [slots][n] meeting set
-    uint64_t *meetw;  // [slots][n] meeting weights (when the set exceeds LDS)
-    int32_t *loff;    // [slots][2][lcap] start of each BFS level in ball
-    int32_t lcap;     // entries per side (diameter bound + 2)
+    uint32_t *code;     // [slots][code_stride] 2-bit level codes per side, 8 vertices a word
+    Sigma *sigma;       // [slots][2][n] sigma_s, sigma_t
+    int32_t *ball;      // [slots][2][n] vertices reached by each side, BFS order
+    int32_t *meet;      // [slots][n] meeting set
+    uint64_t *meetw;    // [slots][n] meeting weights (when the set exceeds LDS)
+    int32_t *loff;      // [slots][2][lcap] start of each BFS level in ball
+    int32_t lcap;       // entries per side (diameter bound + 2)
+    int32_t code_stride;  // words per slot (ceil(n / 8), rounded up to 64 bytes)
 };
 
 struct SampleArgs {
@@ -63,7 +56,9 @@ struct SampleArgs {
     uint64_t seed;
     int64_t lo, hi;   // sample indices of this epoch: [lo, hi)
     int32_t parity;   // epoch parity (selects claim counter, frames, stats)
-    int64_t probe_min;  // expansions of at least this many arcs probe for the meeting first
+    int64_t probe_min;  // >= 0: expansions of at least this many arcs probe for the meeting
+                        // first; -1: probe when D_X * D_Y >= num_arcs
+    int64_t num_arcs;
     int32_t gate;     // -1, or the parity of the previous boundary: if its check
                       // found no violation the run has stopped and this launch exits
     int32_t *frames;  // [2][nframes][n]

@@ -67,12 +67,17 @@ __device__ __forceinline__ uint64_t wg_add_u64(uint64_t *p, uint64_t v)
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ __forceinline__ uint32_t wg_cas_u32(uint32_t *p, uint32_t expected, uint32_t desired)
+__device__ __forceinline__ uint32_t wg_or_u32(uint32_t *p, uint32_t v)
 {
-    __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_WORKGROUP);
-    return expected;  // the value found: == the argument iff the swap happened
+    return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+
+// Level codes.  A neighbour of a vertex on BFS level l lies on level l - 1, l
+// or l + 1 (or is unreached), so (level mod 3) + 1 in two bits per side
+// identifies it; 0 = unreached.  Vertex w's codes sit in word w / 8 at bit
+// 4 (w mod 8) (side s) and 4 (w mod 8) + 2 (side t).
+__device__ __forceinline__ uint32_t level_code(int32_t level) { return (uint32_t)(level % 3) + 1u; }
+__device__ __forceinline__ int code_shift(int32_t w, int side) { return 4 * (w & 7) + 2 * side; }
 
 // 128-bit add into global memory: low word atomically, carry into the high
 // word.  The final value is the exact sum whatever the order of the adds.
@@ -186,6 +191,42 @@ struct Team {
         for (int k = 0; k < WAVES; ++k) t += ((u128)red[2 * k + 1] << 64) | red[2 * k];
         __syncthreads();
         return t;
+    }
+
+    // sums a 64-bit and a 128-bit value over the team with one exchange
+    __device__ static void sum_u64_u128(uint64_t *a, u128 *b, uint64_t *red)
+    {
+        uint64_t x = *a, lo = (uint64_t)*b, hi = (uint64_t)(*b >> 64);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            x += __shfl_xor(x, o, 64);
+            const uint64_t l2 = __shfl_xor(lo, o, 64), h2 = __shfl_xor(hi, o, 64);
+            const uint64_t l = lo + l2;
+            hi = hi + h2 + (l < lo ? 1u : 0u);
+            lo = l;
+        }
+        if (WAVES == 1) {
+            *a = x;
+            *b = ((u128)hi << 64) | lo;
+            return;
+        }
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            red[3 * w] = x;
+            red[3 * w + 1] = lo;
+            red[3 * w + 2] = hi;
+        }
+        __syncthreads();
+        uint64_t tx = 0;
+        u128 tb = 0;
+#pragma unroll
+        for (int k = 0; k < WAVES; ++k) {
+            tx += red[3 * k];
+            tb += ((u128)red[3 * k + 2] << 64) | red[3 * k + 1];
+        }
+        __syncthreads();
+        *a = tx;
+        *b = tb;
     }
 
     __device__ static u128 max_u128(u128 v, uint64_t *red)
@@ -397,7 +438,9 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
     const int lane = threadIdx.x;
     const size_t n = (size_t)a.n;
     const size_t slot = blockIdx.x;
-    VRec *const rec = a.st.rec + slot * n;
+    uint32_t *const code = a.st.code + slot * (size_t)a.st.code_stride;
+    Sigma *const sig0 = a.st.sigma + (2 * slot) * n;
+    Sigma *const sig1 = a.st.sigma + (2 * slot + 1) * n;
     int32_t *const ball0 = a.st.ball + (2 * slot) * n;
     int32_t *const ball1 = a.st.ball + (2 * slot + 1) * n;
     int32_t *const meet = a.st.meet + slot * n;
@@ -441,10 +484,10 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
 
         // -- balanced bidirectional BFS with path counts ----------------------
         if (lane == 0) {
-            rec[s].dist[0] = 1u;
-            rec[t].dist[1] = 1u;
-            rec[s].sig[0] = Sigma{1u, 0u};
-            rec[t].sig[1] = Sigma{1u, 0u};
+            code[s >> 3] |= level_code(0) << code_shift(s, 0);
+            code[t >> 3] |= level_code(0) << code_shift(t, 1);
+            sig0[s] = Sigma{1u, 0u};
+            sig1[t] = Sigma{1u, 0u};
             ball0[0] = s;
             ball1[0] = t;
             loff0[0] = 0;
@@ -463,6 +506,7 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
         for (;;) {
             X = (dsum0 <= dsum1) ? 0 : 1;  // cheaper side; s on ties
             int32_t *const ballx = X ? ball1 : ball0;
+            Sigma *const sigx = X ? sig1 : sig0;
             const int32_t lvlx = X ? lvl1 : lvl0;
             const int32_t flox = X ? flo1 : flo0;
             const int32_t fhix = X ? fhi1 : fhi0;
@@ -478,8 +522,14 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
             // needed (sigma of a meeting vertex is the same sum either way);
             // otherwise the level is expanded in full.  The probe cannot skip a
             // rescaling: it runs only when the frontier's mass is below 2^104.
-            const bool probe = !retry && dsx >= a.probe_min &&
-                               bitw128(X ? fmass1 : fmass0) <= SIGMA_BITS;
+            // Auto rule (probe_min < 0): probe when the arcs leaving X's
+            // frontier are expected to hit Y's frontier at least four times,
+            // D_X D_Y >= 4 x (number of arcs), an arc landing on a vertex with
+            // probability proportional to its degree.
+            const int64_t dsy = X ? dsum0 : dsum1;
+            const bool want_probe = (a.probe_min >= 0) ? (dsx >= a.probe_min)
+                                                       : (dsx * dsy >= 4 * a.num_arcs);
+            const bool probe = !retry && want_probe && bitw128(X ? fmass1 : fmass0) <= SIGMA_BITS;
             if (lane == 0) {
                 if (!retry) {
                     st_vexp += (uint64_t)(fhix - flox);
@@ -488,9 +538,8 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                 sm.nnext = 0;
                 sm.nmeet = 0;
             }
-            const uint32_t enc_new = (uint32_t)lvlx + 2u;  // (dist + 1) of the new level
+            const uint32_t code_new = level_code(lvlx + 1);  // code of the new level
             const int32_t base_new = fhix;
-            u128 mass = 0;  // sum of the frontier's sigma: bounds every new count
             __syncthreads();
             for (int32_t c0 = flox; c0 < fhix; c0 += TEAM) {
                 const int32_t idx = c0 + lane;
@@ -499,8 +548,7 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                     const int32_t u = ballx[idx];
                     const int32_t rs = row_ptr[u];
                     dg = row_ptr[u + 1] - rs;
-                    const Sigma m = rec[u].sig[X];
-                    mass += to128(m);
+                    const Sigma m = sigx[u];
                     sm.cu[lane] = u;
                     sm.crs[lane] = rs;
                     sm.cm[lane] = m;
@@ -510,34 +558,60 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                 sm.cpfx[lane] = ex;
                 const int32_t cnt = min(TEAM, fhix - c0);
                 __syncthreads();
-                for (int32_t e = lane; e < tot; e += TEAM) {
-                    // owner of arc e: the last chunk entry whose prefix is <= e
-                    int32_t lo = 0, hi = cnt;
-                    while (hi - lo > 1) {
-                        const int32_t mid = (lo + hi) >> 1;
-                        if (sm.cpfx[mid] <= e) lo = mid; else hi = mid;
+                // Each lane takes arcs lane, lane + TEAM, ... two at a time: both
+                // owners, column entries and code words are fetched before
+                // either is processed.  A lane's owners only move forward, so
+                // each is found by galloping from the previous one.
+                int32_t own = 0;
+                auto owner_of = [&](int32_t e) {
+                    int32_t step = 1;
+                    while (own + step < cnt && sm.cpfx[own + step] <= e) {
+                        own += step;
+                        step <<= 1;
                     }
-                    const int32_t w = col[sm.crs[lo] + (e - sm.cpfx[lo])];
-                    VRec *const rw = &rec[w];
-                    const uint2 d2 = *reinterpret_cast<const uint2 *>(rw->dist);
-                    uint32_t dx = X ? d2.y : d2.x;
-                    const uint32_t dy = X ? d2.x : d2.y;
+                    int32_t hi = min(own + step, cnt);
+                    while (hi - own > 1) {
+                        const int32_t mid = (own + hi) >> 1;
+                        if (sm.cpfx[mid] <= e) own = mid; else hi = mid;
+                    }
+                    return own;
+                };
+                auto visit = [&](int32_t w, uint32_t word, int32_t o) {
+                    uint32_t *const cw = &code[w >> 3];
+                    const int shx = code_shift(w, X), shy = code_shift(w, X ^ 1);
+                    uint32_t dx = (word >> shx) & 3u;
+                    const uint32_t dy = (word >> shy) & 3u;
                     bool claimed = false;
                     if (dx == 0u && (!probe || dy != 0u)) {
-                        const uint32_t old = wg_cas_u32(&rw->dist[X], 0u, enc_new);
+                        // every claim on this level writes the same code, so an
+                        // OR into a field another lane just set changes nothing
+                        const uint32_t old = (wg_or_u32(cw, code_new << shx) >> shx) & 3u;
                         claimed = (old == 0u);
-                        dx = claimed ? enc_new : old;
+                        dx = claimed ? code_new : old;
                     }
                     const int p = wave_append(claimed, &sm.nnext);
                     if (claimed) ballx[base_new + p] = w;
                     const bool is_meet = claimed && dy != 0u;
                     const int q = wave_append(is_meet, &sm.nmeet);
                     if (is_meet) meet[q] = w;
-                    if (dx == enc_new) atomic_add_sigma(&rw->sig[X], to128(sm.cm[lo]));
+                    if (dx == code_new) atomic_add_sigma(&sigx[w], to128(sm.cm[o]));
+                };
+                for (int32_t e = lane; e < tot; e += 2 * TEAM) {
+                    const int32_t e2 = e + TEAM;
+                    const int32_t o1 = owner_of(e);
+                    const int32_t w1 = col[sm.crs[o1] + (e - sm.cpfx[o1])];
+                    int32_t o2 = o1, w2 = -1;
+                    if (e2 < tot) {
+                        o2 = owner_of(e2);
+                        w2 = col[sm.crs[o2] + (e2 - sm.cpfx[o2])];
+                    }
+                    const uint32_t word1 = code[w1 >> 3];
+                    const uint32_t word2 = (w2 >= 0) ? code[w2 >> 3] : 0u;
+                    visit(w1, word1, o1);
+                    if (w2 >= 0) visit(w2, word2, o2);
                 }
                 __syncthreads();
             }
-            T::sync();
             PHASE_MARK(1);
             nN = sm.nnext;
             nM = sm.nmeet;
@@ -551,11 +625,11 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                 break;
             }
             // rescale the new level if its largest count may reach 2^SIGMA_BITS
-            const u128 mass_all = T::sum_u128(mass, sm.red);
-            if (bitw128(mass_all) > SIGMA_BITS) {
+            // the frontier's mass bounds every new count
+            if (bitw128(X ? fmass1 : fmass0) > SIGMA_BITS) {
                 u128 hm = 0;
                 for (int32_t k = lane; k < nN; k += TEAM) {
-                    const u128 v = to128(rec[ballx[base_new + k]].sig[X]);
+                    const u128 v = to128(sigx[ballx[base_new + k]]);
                     hm = v > hm ? v : hm;
                 }
                 hm = T::max_u128(hm, sm.red);
@@ -564,8 +638,8 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                     const u128 add = ((u128)1 << sh) - 1;
                     for (int32_t k = lane; k < nN; k += TEAM) {
                         const int32_t w = ballx[base_new + k];
-                        const u128 v = (to128(rec[w].sig[X]) + add) >> sh;
-                        rec[w].sig[X] = Sigma{(uint64_t)v, (uint64_t)(v >> 64)};
+                        const u128 v = (to128(sigx[w]) + add) >> sh;
+                        sigx[w] = Sigma{(uint64_t)v, (uint64_t)(v >> 64)};
                     }
                 }
                 T::sync();
@@ -578,10 +652,9 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
             for (int32_t k = lane; k < nN; k += TEAM) {
                 const int32_t w = ballx[base_new + k];
                 ds += (uint64_t)(row_ptr[w + 1] - row_ptr[w]);
-                ms += to128(rec[w].sig[X]);
+                ms += to128(sigx[w]);
             }
-            ds = T::sum_u64(ds, sm.red);
-            ms = T::sum_u128(ms, sm.red);
+            T::sum_u64_u128(&ds, &ms, sm.red);
             if (lane == 0) (X ? loff1 : loff0)[lvlx + 2] = fhix + nN;
             if (X) {
                 flo1 = fhi1;
@@ -612,7 +685,7 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                 U256 pm{0, 0};
                 for (int32_t k = lane; k < nM; k += TEAM) {
                     const int32_t w = meet[k];
-                    const U256 p = mul_128x128(to128(rec[w].sig[0]), to128(rec[w].sig[1]));
+                    const U256 p = mul_128x128(to128(sig0[w]), to128(sig1[w]));
                     if (p.hi > pm.hi || (p.hi == pm.hi && p.lo > pm.lo)) pm = p;
                 }
                 pm = T::max_u256(pm, sm.red);
@@ -622,7 +695,7 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                 for (int32_t k = lane; k < nM; k += TEAM) {
                     const int32_t w = meet[k];
                     const uint64_t wt =
-                        ceil_shr256(mul_128x128(to128(rec[w].sig[0]), to128(rec[w].sig[1])), shp);
+                        ceil_shr256(mul_128x128(to128(sig0[w]), to128(sig1[w])), shp);
                     if (staged) {
                         sm.sv[k] = w;
                         sm.sw[k] = Sigma{wt, 0u};
@@ -634,14 +707,15 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                     vmax = max(vmax, w);
                 }
                 tot = T::sum_u64(tot, sm.red);
-                // team min / max of the ids (as maxima of n - id and id + 1)
+                // team min / max of the ids (as maxima of n - id and id + 1),
+                // needed by the binary search over ids only
                 uint64_t mn = (uint64_t)(uint32_t)(a.n - vmin), mx = (uint64_t)(uint32_t)(vmax + 1);
 #pragma unroll
                 for (int o = 32; o > 0; o >>= 1) {
                     mn = max(mn, (uint64_t)__shfl_xor(mn, o, 64));
                     mx = max(mx, (uint64_t)__shfl_xor(mx, o, 64));
                 }
-                if (T::WAVES > 1) {
+                if (T::WAVES > 1 && nM > TEAM) {
                     const int wv = lane >> 6;
                     if ((lane & 63) == 0) {
                         sm.red[2 * wv] = mn;
@@ -656,26 +730,38 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                 }
                 T::sync();  // staged weights visible to the whole team
                 const uint64_t r = __umul64hi(philox_u64(a.seed, (uint64_t)i, 1u), tot);
-                // smallest id v whose inclusive prefix (ascending ids) exceeds r
-                int32_t lo = a.n - (int32_t)mn, hi = (int32_t)mx - 1;
-                while (lo < hi) {
-                    const int32_t mid = lo + ((hi - lo) >> 1);
-                    uint64_t part = 0;
-                    if (staged) {
-                        for (int32_t k = lane; k < nM; k += TEAM)
-                            part += (sm.sv[k] <= mid) ? sm.sw[k].lo : 0u;
-                    } else {
-                        for (int32_t k = lane; k < nM; k += TEAM)
-                            part += (meet[k] <= mid) ? meetw[k] : 0u;
+                if (nM <= TEAM) {
+                    // rank by scanning the staged set: the element whose
+                    // ascending-id inclusive prefix first exceeds r
+                    if (lane == 0) sm.pick = -1;
+                    __syncthreads();
+                    pick_by_id_prefix<TEAM>(sm.sv, sm.sw, nM, (u128)r, &sm.pick);
+                    __syncthreads();
+                    v = sm.pick;
+                } else {
+                    // smallest id v whose inclusive prefix (ascending ids) exceeds r
+                    int32_t lo = a.n - (int32_t)mn, hi = (int32_t)mx - 1;
+                    while (lo < hi) {
+                        const int32_t mid = lo + ((hi - lo) >> 1);
+                        uint64_t part = 0;
+                        if (staged) {
+                            for (int32_t k = lane; k < nM; k += TEAM)
+                                part += (sm.sv[k] <= mid) ? sm.sw[k].lo : 0u;
+                        } else {
+                            for (int32_t k = lane; k < nM; k += TEAM)
+                                part += (meet[k] <= mid) ? meetw[k] : 0u;
+                        }
+                        part = T::sum_u64(part, sm.red);
+                        if (part > r) hi = mid; else lo = mid + 1;
                     }
-                    part = T::sum_u64(part, sm.red);
-                    if (part > r) hi = mid; else lo = mid + 1;
+                    v = lo;
                 }
-                v = lo;
             }
             PHASE_MARK(3);
-            const uint2 dv = *reinterpret_cast<const uint2 *>(rec[v].dist);
-            if (lane == 0 && dv.x > 1u && dv.y > 1u) {
+            // v's distances: one more than side X's frontier level, side Y's level
+            const int32_t dv0 = (X == 0) ? lvl0 + 1 : lvl0;
+            const int32_t dv1 = (X == 1) ? lvl1 + 1 : lvl1;
+            if (lane == 0 && dv0 > 0 && dv1 > 0) {
                 atomicAdd(&frame[v], 1);
                 ++st_int;
             }
@@ -683,15 +769,14 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
             for (int side = 0; side < 2 && ok; ++side) {
                 const int32_t *const balls = side ? ball1 : ball0;
                 const int32_t *const loffs = side ? loff1 : loff0;
+                const Sigma *const sg = side ? sig1 : sig0;
                 int32_t x = v;
-                for (;;) {
-                    const uint32_t ex = rec[x].dist[side];
-                    if (ex <= 2u) break;  // x at distance <= 1: the root is next
-                    const uint32_t want = ex - 1u;
+                for (int32_t dxv = side ? dv1 : dv0; dxv > 1; --dxv) {  // x on level dxv
+                    const uint32_t want = level_code(dxv - 1);
                     const int32_t rs = row_ptr[x], deg = row_ptr[x + 1] - rs;
-                    // predecessors = x's neighbours on level dist(x) - 1 of this side
-                    const int32_t llo = loffs[ex - 2u], lhi = loffs[ex - 1u];
-                    const uint32_t j = 2u * (ex - 1u) + (uint32_t)side;
+                    // predecessors = x's neighbours on level dxv - 1 of this side
+                    const int32_t llo = loffs[dxv - 1], lhi = loffs[dxv];
+                    const uint32_t j = 2u * (uint32_t)dxv + (uint32_t)side;
                     const uint64_t U = philox_u64(a.seed, (uint64_t)i, j);
                     if (lane == 0) {
                         sm.pick = -1;
@@ -708,7 +793,7 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                             const int at = wave_append(hit, &sm.ncand);
                             if (hit && at < STAGE) {
                                 sm.sv[at] = p;
-                                sm.sw[at] = rec[p].sig[side];
+                                sm.sw[at] = sg[p];
                             }
                         }
                         __syncthreads();
@@ -730,16 +815,19 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                         int32_t e = e0;
                         for (; e + 4 <= e1; e += 4) {  // four independent loads in flight
                             const int32_t p0 = col[e], p1 = col[e + 1], p2 = col[e + 2], p3 = col[e + 3];
-                            const uint32_t d0 = rec[p0].dist[side], d1 = rec[p1].dist[side];
-                            const uint32_t d2 = rec[p2].dist[side], d3 = rec[p3].dist[side];
-                            if (d0 == want) part += to128(rec[p0].sig[side]);
-                            if (d1 == want) part += to128(rec[p1].sig[side]);
-                            if (d2 == want) part += to128(rec[p2].sig[side]);
-                            if (d3 == want) part += to128(rec[p3].sig[side]);
+                            const uint32_t c0 = (code[p0 >> 3] >> code_shift(p0, side)) & 3u;
+                            const uint32_t c1 = (code[p1 >> 3] >> code_shift(p1, side)) & 3u;
+                            const uint32_t c2 = (code[p2 >> 3] >> code_shift(p2, side)) & 3u;
+                            const uint32_t c3 = (code[p3 >> 3] >> code_shift(p3, side)) & 3u;
+                            if (c0 == want) part += to128(sg[p0]);
+                            if (c1 == want) part += to128(sg[p1]);
+                            if (c2 == want) part += to128(sg[p2]);
+                            if (c3 == want) part += to128(sg[p3]);
                         }
                         for (; e < e1; ++e) {
                             const int32_t p = col[e];
-                            if (rec[p].dist[side] == want) part += to128(rec[p].sig[side]);
+                            if (((code[p >> 3] >> code_shift(p, side)) & 3u) == want)
+                                part += to128(sg[p]);
                         }
                         u128 tot;
                         const u128 ex_pre = T::excl_scan_u128(part, &tot, sm.red);
@@ -748,8 +836,8 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                             u128 acc = ex_pre;
                             for (int32_t q = e0; q < e1; ++q) {
                                 const int32_t p = col[q];
-                                if (rec[p].dist[side] != want) continue;
-                                acc += to128(rec[p].sig[side]);
+                                if (((code[p >> 3] >> code_shift(p, side)) & 3u) != want) continue;
+                                acc += to128(sg[p]);
                                 if (acc > r) {
                                     sm.pick = p;
                                     break;
@@ -778,15 +866,17 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
         PHASE_MARK(4);
 
         // -- clear what this sample touched ----------------------------------
-        const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
-        for (int32_t k = lane; k < bend0 + bend1; k += TEAM) {
-            const int32_t w = (k < bend0) ? ball0[k] : ball1[k - bend0];
-            uint4 *const r4 = reinterpret_cast<uint4 *>(&rec[w]);
-            // the whole 64-byte record: a full-sector write needs no read
-            r4[0] = z4;
-            r4[1] = z4;
-            r4[2] = z4;
-            r4[3] = z4;
+        // a code word holds only codes of vertices reached by this sample, so
+        // zeroing whole words restores the all-zero state
+        for (int32_t k = lane; k < bend0; k += TEAM) {
+            const int32_t w = ball0[k];
+            code[w >> 3] = 0u;
+            sig0[w] = Sigma{0u, 0u};
+        }
+        for (int32_t k = lane; k < bend1; k += TEAM) {
+            const int32_t w = ball1[k];
+            code[w >> 3] = 0u;
+            sig1[w] = Sigma{0u, 0u};
         }
         PHASE_MARK(5);
     }
