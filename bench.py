@@ -59,7 +59,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rmat18", choices=["rmat18", "pgrid1024", "er4096"])
+    ap.add_argument("--workload", default="rmat18",
+                    choices=["rmat18", "pgrid1024", "er4096", "batch64"])
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--team", type=int, default=0)
     ap.add_argument("--slots", type=int, default=0)
@@ -90,6 +91,8 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": src.numel() * 4}))
         return 0
+    if args.gpus == 1 and args.workload == "batch64":
+        return bench_batch(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the sampling "
               "path here is single-device; see DESIGN.md for how it would shard.", file=sys.stderr)
@@ -184,6 +187,85 @@ def main() -> int:
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, eps, delta, args.seed, n_check, args.cpu_repeats)
     dev.close()
+    print(json.dumps(out))
+    return 0
+
+
+def bench_batch(args) -> int:
+    """The batched workload: 64 queries (32 R-MAT of scales 12-16, 32 random
+    hyperbolic graphs of 2^14-2^17 vertices; eps from {0.05, 0.02, 0.01}),
+    run one after another through Graph.run and together through one Batch,
+    on the same GPU.  value = samples/s of the batched form."""
+    import torch
+
+    from paper_1903_09422_amd import Batch, Graph, graphs
+
+    pool = graphs.batch_pool()
+    handles = [Graph.from_csr(g) for g, *_ in pool]
+    for h, (g, eps, delta, n_check, seed) in zip(handles, pool):
+        h.set_param("check_interval", n_check)
+    batch = Batch()
+    batch.set_param("team", args.team)
+    batch.set_param("slots", args.slots)
+    batch.set_param("probe_min", args.probe_min)
+    for h, (g, eps, delta, n_check, seed) in zip(handles, pool):
+        batch.add(h, eps, delta, seed, n_check)
+
+    def serial():
+        tot = 0
+        for h, (g, eps, delta, n_check, seed) in zip(handles, pool):
+            h.run(eps, delta, seed)
+            tot += h.stats()["tau"]
+        return tot
+
+    def batched():
+        batch.run()
+        return sum(batch.stats(k)["tau"] for k in range(len(pool)))
+
+    for _ in range(max(args.warmup, 1)):
+        serial()
+        batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s_serial = sum(serial() for _ in range(args.steps))
+    t_serial = time.perf_counter() - t0
+    lat = []
+    t0 = time.perf_counter()
+    s_batch = 0
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        s_batch += batched()
+        lat.append((time.perf_counter() - ts) * 1e3)
+    t_batch = time.perf_counter() - t0
+    assert s_serial == s_batch
+    out = {
+        "metric": "samples/s (KADABRA adaptive sampling, 64-query batch)",
+        "value": s_batch / t_batch,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_batch * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "batch64: 32 R-MAT (scale 12 + k mod 5, edge factor 16) + 32 "
+                               "threshold random hyperbolic graphs (n = 2^(14 + k mod 4), mean "
+                               "degree 10, exponent 2.8); eps from {0.05, 0.02, 0.01}, delta 0.1, "
+                               "checks every 1024 samples",
+                   "queries": len(pool), "samples_per_step": s_batch // args.steps,
+                   "mapping": {"team": batch.get_param("last_team"),
+                               "slots": batch.get_param("last_slots")}},
+        "serial_samples_per_s": s_serial / t_serial,
+        "serial_ms_per_step": t_serial * 1e3 / args.steps,
+        "speedup_vs_serial": (s_batch / t_batch) / (s_serial / t_serial),
+        "batch_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+    }
+    batch.close()
+    for h in handles:
+        h.close()
     print(json.dumps(out))
     return 0
 

@@ -162,6 +162,57 @@ int kadabra_get_decisions(const kadabra_graph *g, int8_t *out, int64_t cap, int6
 int kadabra_eval_stop_fg(int32_t n, const int32_t *counts, int64_t tau, int64_t omega, double L,
                          double *f, double *g);
 
+/*
+ * Autotuner.  Times a fixed set of mapping candidates (workgroup or
+ * wavefront per sample, the number of samples in flight, the meeting probe on
+ * or off) on the first trial_samples samples of this graph's query (eps,
+ * delta; a fixed calibration seed; no stop checks) and keeps the fastest in
+ * the handle's parameters ("team", "slots", "probe_min").  Results never
+ * depend on these parameters.  Errors: EINVAL, ERANGE, ENOMEM, EDEVICE.
+ */
+int kadabra_autotune(kadabra_graph *g, double eps, double delta, int64_t trial_samples);
+
+/* ------------------------------------------------------------------------ */
+/* Batches: many queries, on any number of graphs, run in shared launches:   */
+/* every sampling launch carries the current epoch of every active query and */
+/* one merge-and-check launch handles all their boundaries.  Each query's    */
+/* result is exactly the one kadabra_run gives for it alone.                 */
+/* ------------------------------------------------------------------------ */
+typedef struct kadabra_batch kadabra_batch;
+
+/* Creates an empty batch on the current device.  Errors: ENOMEM, EDEVICE. */
+int kadabra_batch_create(kadabra_batch **out);
+
+/* As kadabra_set_param for the batch's mapping ("team", "slots", "frames",
+ * "overlap", "probe_min", "test_fail_alloc"); "check_interval" is per query. */
+int kadabra_batch_set_param(kadabra_batch *b, const char *key, int64_t value);
+int kadabra_batch_get_param(const kadabra_batch *b, const char *key, int64_t *value);
+int kadabra_batch_set_stream(kadabra_batch *b, void *hip_stream);
+
+/*
+ * Adds a query (graph g, eps, delta, seed, check interval N) and returns its
+ * index.  g must stay alive until the batch is cleared or destroyed.
+ * Errors: EINVAL (parameters), ERANGE (omega >= 2^31).
+ */
+int kadabra_batch_add(kadabra_batch *b, const kadabra_graph *g, double eps, double delta,
+                      uint64_t seed, int64_t check_interval, int32_t *index);
+
+/* Runs every query of the batch to completion (blocking).  Errors: ESTATE
+ * (empty batch), ENOMEM, EDEVICE. */
+int kadabra_batch_run(kadabra_batch *b);
+
+/* Autotuner for the batch's mapping, as kadabra_autotune. */
+int kadabra_batch_autotune(kadabra_batch *b, int64_t trial_samples);
+
+/* Reads query `index` of the last completed batch run (as kadabra_get_scores).
+ * Errors: EINVAL (index), ESTATE. */
+int kadabra_batch_get_scores(const kadabra_batch *b, int32_t index, double *scores,
+                             int32_t *counts, kadabra_stats *stats);
+
+/* Drops all queries (the device pool is kept for the next ones). */
+int kadabra_batch_clear(kadabra_batch *b);
+void kadabra_batch_destroy(kadabra_batch *b);
+
 /* Asks a run in progress on another thread to stop at its next boundary
  * (kadabra_run then returns ECANCELED).  Safe to call concurrently. */
 int kadabra_cancel(kadabra_graph *g);

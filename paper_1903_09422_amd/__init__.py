@@ -20,7 +20,7 @@ import numpy as np
 
 from ._lib import EXPORTS, KadabraError, Stats, check, lib  # noqa: F401
 
-__all__ = ["Graph", "RunResult", "KadabraError", "eval_stop_fg", "lib"]
+__all__ = ["Graph", "Batch", "RunResult", "KadabraError", "eval_stop_fg", "lib"]
 
 
 @dataclass
@@ -92,6 +92,12 @@ class Graph:
         return RunResult(tau=int(st.tau), counts=counts, scores=scores, stats=st.as_dict(),
                          decisions=dec[: int(cnt.value)].copy())
 
+    def autotune(self, eps: float, delta: float, trial_samples: int = 8192) -> dict:
+        """Pick the fastest mapping (team, slots, probe) on a trial prefix;
+        results never depend on it.  Returns the chosen parameters."""
+        check(lib().kadabra_autotune(self._h, float(eps), float(delta), int(trial_samples)))
+        return {k: self.get_param(k) for k in ("team", "slots", "probe_min")}
+
     def stats(self) -> dict:
         st = Stats()
         check(lib().kadabra_get_scores(self._h, None, None, C.byref(st)))
@@ -112,6 +118,83 @@ class Graph:
     def close(self) -> None:
         if getattr(self, "_h", None):
             lib().kadabra_destroy_graph(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many queries (graph, eps, delta, seed, check interval) run in shared
+    launches; each result equals the query's own Graph.run result."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        check(lib().kadabra_batch_create(C.byref(h)))
+        self._h = h
+        self._graphs = []  # keep graph handles alive while queries reference them
+        self._stream_ref = None
+
+    def set_param(self, key: str, value: int) -> None:
+        check(lib().kadabra_batch_set_param(self._h, key.encode(), int(value)))
+
+    def get_param(self, key: str) -> int:
+        v = C.c_int64()
+        check(lib().kadabra_batch_get_param(self._h, key.encode(), C.byref(v)))
+        return int(v.value)
+
+    def set_stream(self, stream) -> None:
+        ptr = None if stream is None else (stream if isinstance(stream, int) else int(stream.cuda_stream))
+        self._stream_ref = stream
+        check(lib().kadabra_batch_set_stream(self._h, ptr))
+
+    def add(self, graph: Graph, eps: float, delta: float, seed: int, check_interval: int) -> int:
+        idx = C.c_int32()
+        check(lib().kadabra_batch_add(self._h, graph._h, float(eps), float(delta), int(seed),
+                                      int(check_interval), C.byref(idx)))
+        self._graphs.append(graph)
+        return int(idx.value)
+
+    def run(self) -> None:
+        check(lib().kadabra_batch_run(self._h))
+
+    def autotune(self, trial_samples: int = 4096) -> dict:
+        check(lib().kadabra_batch_autotune(self._h, int(trial_samples)))
+        return {k: self.get_param(k) for k in ("team", "slots", "probe_min")}
+
+    def result(self, index: int) -> RunResult:
+        if not 0 <= index < len(self._graphs):  # let the library report the bad index
+            check(lib().kadabra_batch_get_scores(self._h, int(index), None, None, None))
+        n = self._graphs[index].n
+        scores = np.empty(n, dtype=np.float64)
+        counts = np.empty(n, dtype=np.int32)
+        st = Stats()
+        check(lib().kadabra_batch_get_scores(self._h, int(index), scores.ctypes.data,
+                                             counts.ctypes.data, C.byref(st)))
+        return RunResult(tau=int(st.tau), counts=counts, scores=scores, stats=st.as_dict(),
+                         decisions=np.empty(0, dtype=np.int8))
+
+    def stats(self, index: int) -> dict:
+        st = Stats()
+        check(lib().kadabra_batch_get_scores(self._h, int(index), None, None, C.byref(st)))
+        return st.as_dict()
+
+    def clear(self) -> None:
+        check(lib().kadabra_batch_clear(self._h))
+        self._graphs = []
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().kadabra_batch_destroy(self._h)
             self._h = None
 
     def __enter__(self):

@@ -20,8 +20,12 @@ EXPORTS = (
     "kadabra_create_graph", "kadabra_set_param", "kadabra_get_param", "kadabra_set_stream",
     "kadabra_run", "kadabra_get_scores", "kadabra_get_scores_device", "kadabra_get_decisions",
     "kadabra_eval_stop_fg", "kadabra_cancel", "kadabra_destroy_graph", "kadabra_last_error",
-    "kadabra_version",
+    "kadabra_version", "kadabra_autotune", "kadabra_batch_create", "kadabra_batch_set_param",
+    "kadabra_batch_get_param", "kadabra_batch_set_stream", "kadabra_batch_add", "kadabra_batch_run",
+    "kadabra_batch_autotune", "kadabra_batch_get_scores", "kadabra_batch_clear",
+    "kadabra_batch_destroy",
 )
+VOID_FUNCS = ("kadabra_destroy_graph", "kadabra_batch_destroy", "kadabra_last_error")
 
 
 class KadabraError(RuntimeError):
@@ -77,8 +81,21 @@ def lib() -> C.CDLL:
     L.kadabra_last_error.argtypes = []
     L.kadabra_last_error.restype = C.c_char_p
     L.kadabra_version.argtypes = []
+    L.kadabra_autotune.argtypes = [vp, C.c_double, C.c_double, C.c_int64]
+    L.kadabra_batch_create.argtypes = [C.POINTER(vp)]
+    L.kadabra_batch_set_param.argtypes = [vp, C.c_char_p, C.c_int64]
+    L.kadabra_batch_get_param.argtypes = [vp, C.c_char_p, i64p]
+    L.kadabra_batch_set_stream.argtypes = [vp, vp]
+    L.kadabra_batch_add.argtypes = [vp, vp, C.c_double, C.c_double, C.c_uint64, C.c_int64,
+                                    C.POINTER(C.c_int32)]
+    L.kadabra_batch_run.argtypes = [vp]
+    L.kadabra_batch_autotune.argtypes = [vp, C.c_int64]
+    L.kadabra_batch_get_scores.argtypes = [vp, C.c_int32, vp, vp, C.POINTER(Stats)]
+    L.kadabra_batch_clear.argtypes = [vp]
+    L.kadabra_batch_destroy.argtypes = [vp]
+    L.kadabra_batch_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("kadabra_destroy_graph", "kadabra_last_error"):
+        if name not in VOID_FUNCS:
             getattr(L, name).restype = C.c_int
     _lib = L
     return L

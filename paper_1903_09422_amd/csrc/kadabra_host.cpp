@@ -1,14 +1,22 @@
-// kadabra_host.cpp -- C ABI and host driver of the gfx950 KADABRA library.
+// kadabra_host.cpp -- C ABI and host runtime of the gfx950 KADABRA library.
 //
 // Host side: input validation, graph-only preprocessing (components and the
 // vertex-diameter bound, Section 2.3 / Appendix C.1), omega and L, device
-// memory, and the epoch loop of Algorithm 1 with checks every N samples
-// (Appendix C.2).  Per epoch k the stream runs
-//     sample_kernel(k)      samples [B_{k-1}, B_k) into the frames of parity k
-//     merge_check_kernel(k) counters += frames; stopping rule on [0, B_k)
-// and the host reads one flag.  With overlap on, sample_kernel(k+1) is queued
-// before the flag of epoch k is read and is discarded if epoch k stops: the
-// counters checked at B_k hold exactly samples [0, B_k) either way.
+// memory, and the adaptive loop of Algorithm 1 with checks every N samples
+// (Appendix C.2), driven for any number of concurrent queries:
+//
+//   Runner      the device engine: a pool of sample slots shared by all
+//               queries, a control block per query, and the round loop.  In a
+//               round the stream runs
+//                 sample_kernel   the next epoch [B_{k-1}, B_k) of every active query
+//                 merge_check     counters += frames; stopping rule on [0, B_k)
+//                 copy            every query's control block to the host
+//               and, with overlap on, the following epoch's samples are queued
+//               before the host reads the flags; a query that stopped makes
+//               them exit on the device (the counters checked at B_k hold
+//               exactly samples [0, B_k) either way).
+//   kadabra_graph   one graph on the device, running one query at a time.
+//   kadabra_batch   many queries on many graphs in the same launches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,6 +27,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -49,6 +59,12 @@ int fail(int code, const char *fmt, ...)
                         "%s: %s", #expr, hipGetErrorString(e_));                              \
     } while (0)
 
+#define OK_OR_RETURN(expr)           \
+    do {                             \
+        const int rc_ = (expr);      \
+        if (rc_ != KADABRA_OK) return rc_; \
+    } while (0)
+
 constexpr int32_t kMaxN = 1 << 23;       // n and every degree stay below 2^23
 constexpr int64_t kMaxOmega = INT32_MAX; // int32 counters
 
@@ -65,102 +81,24 @@ hipError_t dev_alloc(void **p, size_t bytes, int64_t *fail_countdown = nullptr)
     return hipMalloc(p, bytes);
 }
 
+template <class T>
+hipError_t alloc_n(T **p, size_t count, int64_t *fail_countdown = nullptr)
+{
+    return dev_alloc(reinterpret_cast<void **>(p), count * sizeof(T), fail_countdown);
+}
+
 void dev_free(void *p)
 {
     if (p) (void)hipFree(p);
 }
 
-}  // namespace
-
-struct kadabra_graph {
-    int32_t n = 0;
-    int64_t arcs = 0;
-    int32_t max_deg = 0;
-    int32_t vd = 1;
-    int32_t ncomp = 0;
-    int device = 0;
-    int num_cu = 0;
-    hipStream_t stream = nullptr;
-    hipStream_t own_stream = nullptr;
-    int32_t *d_row_ptr = nullptr, *d_col = nullptr, *d_comp = nullptr;
-
-    // parameters
-    int64_t check_interval = 1024;
-    int team = 0;
-    int64_t slots = 0;
-    int frames = 1;
-    int overlap = 1;
-    int64_t fail_alloc = 0;  // test hook: the fail_alloc-th run-buffer allocation fails
-    int64_t probe_min = -1;  // meeting-probe threshold in arcs; -1 = auto
-
-    // run buffers (kept across runs; grown when needed)
-    int rb_team = 0;
-    int64_t rb_slots = 0;
-    int rb_frames = 0;
-    kd::SlotState st{};
-    int32_t *d_counts = nullptr;
-    int32_t *d_frames = nullptr;
-    kd::Control *d_ctl = nullptr;
-    double *d_scores = nullptr;
-    int32_t *h_flags = nullptr;  // pinned: violation flags of the two parities
-    bool state_dirty = true;     // slot state must be cleared before sampling
-    hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_flag[2] = {nullptr, nullptr};
-    hipEvent_t ev_ks[2] = {nullptr, nullptr}, ev_ke[2] = {nullptr, nullptr};  // sampling launches
-
-    // last result
-    bool have_result = false;
-    int64_t tau = 0, omega = 0, epochs = 0, decision = 0;
-    double L = 0.0, ms_sampling = 0.0, ms_total = 0.0, ms_kernels = 0.0;
-    int64_t work[kd::ST_COUNT] = {};
-    std::vector<int8_t> decisions;
-    std::atomic<int> cancel{0};
-
-    ~kadabra_graph()
-    {
-        release_run_buffers();
-        dev_free(d_row_ptr);
-        dev_free(d_col);
-        dev_free(d_comp);
-        dev_free(d_scores);
-        if (h_flags) (void)hipHostFree(h_flags);
-        for (hipEvent_t e : {ev_start, ev_stop, ev_flag[0], ev_flag[1], ev_ks[0], ev_ks[1], ev_ke[0], ev_ke[1]})
-            if (e) (void)hipEventDestroy(e);
-        if (own_stream) (void)hipStreamDestroy(own_stream);
-    }
-
-    void release_run_buffers()
-    {
-        dev_free(st.code);
-        dev_free(st.sigma);
-        dev_free(st.loff);
-        dev_free(st.ball);
-        dev_free(st.meet);
-        dev_free(st.meetw);
-        dev_free(d_counts);
-        dev_free(d_frames);
-        dev_free(d_ctl);
-        st = kd::SlotState{};
-        d_counts = nullptr;
-        d_frames = nullptr;
-        d_ctl = nullptr;
-        rb_team = 0;
-        rb_slots = 0;
-        rb_frames = 0;
-        state_dirty = true;
-    }
-};
-
-namespace {
-
-// Bytes of per-slot sampling state for a graph of n vertices.
-int32_t code_stride(int32_t n) { return ((n + 7) / 8 + 15) / 16 * 16; }
-
-size_t slot_bytes(int32_t n, int32_t lcap)
+template <class T>
+void dev_release(T *&p)
 {
-    return (size_t)code_stride(n) * 4 +
-           (size_t)n * (2 * sizeof(kd::Sigma) + 2 * sizeof(int32_t) + sizeof(int32_t) + sizeof(uint64_t)) +
-           2 * (size_t)lcap * sizeof(int32_t);
+    dev_free(p);
+    p = nullptr;
 }
+
 
 int validate_csr(int32_t n, int64_t num_arcs, const int32_t *row_ptr, const int32_t *col,
                  int32_t *max_deg_out)
@@ -262,184 +200,697 @@ int64_t omega_of(int32_t vd, double eps, double delta)
     return (int64_t)std::ceil(w);
 }
 
-int ensure_run_buffers(kadabra_graph *g, int team, int64_t slots, int frames)
+
+int32_t code_stride_for(int64_t nstride) { return (int32_t)(((nstride + 7) / 8 + 15) / 16 * 16); }
+
+// Bytes of one sample slot for graphs of up to nstride vertices.
+size_t slot_bytes(int64_t nstride, int32_t lcap)
 {
-    if (g->rb_team == team && g->rb_slots == slots && g->rb_frames == frames && g->d_ctl)
-        return KADABRA_OK;
-    g->release_run_buffers();
-    const size_t n = (size_t)g->n;
-    const size_t S = (size_t)slots;
-    const int32_t lcap = g->vd + 2;  // a side reaches at most diameter <= VD - 1 levels
-    const int32_t cstride = code_stride(g->n);
-    HIP_OR_FAIL(dev_alloc((void **)&g->st.code, S * (size_t)cstride * sizeof(uint32_t), &g->fail_alloc));
-    HIP_OR_FAIL(dev_alloc((void **)&g->st.sigma, S * 2 * n * sizeof(kd::Sigma), &g->fail_alloc));
-    HIP_OR_FAIL(dev_alloc((void **)&g->st.loff, S * 2 * (size_t)lcap * sizeof(int32_t), &g->fail_alloc));
-    g->st.lcap = lcap;
-    g->st.code_stride = cstride;
-    HIP_OR_FAIL(dev_alloc((void **)&g->st.ball, S * 2 * n * sizeof(int32_t), &g->fail_alloc));
-    HIP_OR_FAIL(dev_alloc((void **)&g->st.meet, S * n * sizeof(int32_t), &g->fail_alloc));
-    HIP_OR_FAIL(dev_alloc((void **)&g->st.meetw, S * n * sizeof(uint64_t), &g->fail_alloc));
-    HIP_OR_FAIL(dev_alloc((void **)&g->d_counts, n * sizeof(int32_t), &g->fail_alloc));
-    HIP_OR_FAIL(dev_alloc((void **)&g->d_frames, 2 * (size_t)frames * n * sizeof(int32_t), &g->fail_alloc));
-    HIP_OR_FAIL(dev_alloc((void **)&g->d_ctl, sizeof(kd::Control), &g->fail_alloc));
-    g->rb_team = team;
-    g->rb_slots = slots;
-    g->rb_frames = frames;
-    g->state_dirty = true;
+    return (size_t)code_stride_for(nstride) * 4 +
+           (size_t)nstride * (2 * sizeof(kd::Sigma) + 2 * sizeof(int32_t) + sizeof(int32_t) + sizeof(uint64_t)) +
+           2 * (size_t)lcap * sizeof(int32_t);
+}
+
+// Run parameters (none but check_interval changes a result).
+struct Params {
+    int64_t check_interval = 1024;
+    int team = 0;            // 0 auto, 64, 256
+    int64_t slots = 0;       // 0 auto
+    int frames = 1;
+    int overlap = 1;
+    int64_t probe_min = -1;  // -1 auto rule
+    int64_t fail_alloc = 0;  // test hook
+};
+
+int set_common_param(Params &p, const char *key, int64_t value, bool *known)
+{
+    *known = true;
+    if (!strcmp(key, "check_interval")) {
+        if (value < 1 || value > INT32_MAX) return fail(KADABRA_EINVAL, "check_interval must be in [1, 2^31)");
+        p.check_interval = value;
+    } else if (!strcmp(key, "team")) {
+        if (value != 0 && value != 64 && value != 256) return fail(KADABRA_EINVAL, "team must be 0, 64 or 256");
+        p.team = (int)value;
+    } else if (!strcmp(key, "slots")) {
+        if (value < 0 || value > (1 << 20)) return fail(KADABRA_EINVAL, "slots must be in [0, 2^20]");
+        p.slots = value;
+    } else if (!strcmp(key, "frames")) {
+        if (value < 1 || value > 4096) return fail(KADABRA_EINVAL, "frames must be in [1, 4096]");
+        p.frames = (int)value;
+    } else if (!strcmp(key, "overlap")) {
+        if (value != 0 && value != 1) return fail(KADABRA_EINVAL, "overlap must be 0 or 1");
+        p.overlap = (int)value;
+    } else if (!strcmp(key, "probe_min")) {
+        if (value < -1) return fail(KADABRA_EINVAL, "probe_min must be >= -1");
+        p.probe_min = value;
+    } else if (!strcmp(key, "test_fail_alloc")) {
+        if (value < 0) return fail(KADABRA_EINVAL, "test_fail_alloc must be >= 0");
+        p.fail_alloc = value;
+    } else {
+        *known = false;
+    }
     return KADABRA_OK;
 }
 
-// Mapping choices (none of them changes the result).
-void choose_mapping(const kadabra_graph *g, int *team, int64_t *slots)
+int get_common_param(const Params &p, const char *key, int64_t *value)
 {
-    int tm = g->team;
-    if (tm == 0) tm = 256;
-    int64_t sl = g->slots;
-    if (sl == 0) {
-        const int per_cu = (tm == 64) ? 8 : 4;
-        sl = (int64_t)std::max(g->num_cu, 1) * per_cu;
-        size_t free_b = 0, total_b = 0;
-        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0) {
-            const int64_t fit = (int64_t)((free_b / 2) / slot_bytes(g->n, g->vd + 2));
-            sl = std::min(sl, std::max<int64_t>(fit, 1));
-        }
-    }
-    *team = tm;
-    *slots = std::max<int64_t>(sl, 1);
+    if (!strcmp(key, "check_interval")) *value = p.check_interval;
+    else if (!strcmp(key, "team")) *value = p.team;
+    else if (!strcmp(key, "slots")) *value = p.slots;
+    else if (!strcmp(key, "frames")) *value = p.frames;
+    else if (!strcmp(key, "overlap")) *value = p.overlap;
+    else if (!strcmp(key, "probe_min")) *value = p.probe_min;
+    else return 1;
+    return 0;
 }
 
-int run_impl(kadabra_graph *g, double eps, double delta, uint64_t seed)
-{
-    const auto t_wall0 = std::chrono::steady_clock::now();
-    g->have_result = false;
-    g->cancel.store(0);
-    if (!(eps > 0.0 && eps < 1.0)) return fail(KADABRA_EINVAL, "eps must be in (0, 1)");
-    if (!(delta > 0.0 && delta < 1.0)) return fail(KADABRA_EINVAL, "delta must be in (0, 1)");
-    const int64_t omega = omega_of(g->vd, eps, delta);
-    if (omega > kMaxOmega || omega < 1)
-        return fail(KADABRA_ERANGE, "omega = %lld samples exceeds the int32 counters",
-                    (long long)omega);
-    const double L = std::log(4.0 * (double)g->n / delta);
-    const int64_t N = g->check_interval;
-
-    int team;
-    int64_t slots;
-    choose_mapping(g, &team, &slots);
-    if (int rc = ensure_run_buffers(g, team, slots, g->frames)) return rc;
-
-    hipStream_t s = g->stream;
-    const size_t n = (size_t)g->n;
-    if (g->state_dirty) {
-        HIP_OR_FAIL(kd::launch_fill_u32(g->st.code, (size_t)slots * g->st.code_stride, 0u, s));
-        HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)g->st.sigma, (size_t)slots * n * 8, 0u, s));
-        g->state_dirty = false;
+// A graph resident on the device, plus what depends on the graph only.
+struct GraphData {
+    int32_t n = 0;
+    int64_t arcs = 0;
+    int32_t max_deg = 0;
+    int32_t vd = 1;
+    int32_t ncomp = 0;
+    int32_t *d_row_ptr = nullptr, *d_col = nullptr, *d_comp = nullptr;
+    ~GraphData()
+    {
+        dev_free(d_row_ptr);
+        dev_free(d_col);
+        dev_free(d_comp);
     }
-    HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)g->d_counts, n, 0u, s));
-    HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)g->d_frames, 2 * (size_t)g->frames * n, 0u, s));
-    HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)g->d_ctl, sizeof(kd::Control) / 4, 0u, s));
+};
 
-    kd::SampleArgs sa{};
-    sa.row_ptr = g->d_row_ptr;
-    sa.col = g->d_col;
-    sa.comp = g->d_comp;
-    sa.n = g->n;
-    sa.nframes = g->frames;
-    sa.seed = seed;
-    sa.probe_min = g->probe_min;
-    sa.num_arcs = g->arcs;
-    sa.frames = g->d_frames;
-    sa.ctl = g->d_ctl;
-    sa.st = g->st;
-    kd::CheckArgs ca{};
-    ca.counts = g->d_counts;
-    ca.frames = g->d_frames;
-    ca.n = g->n;
-    ca.nframes = g->frames;
-    ca.omega = omega;
-    ca.L = L;
-    ca.eps = eps;
-    ca.ctl = g->d_ctl;
-
-    g->decisions.clear();
-    HIP_OR_FAIL(hipEventRecord(g->ev_start, s));
-    int64_t k = 0, lo = 0, tau = 0;
-    int decision = 0;
-    bool next_launched = false;
+// One adaptive run.
+struct Query {
+    const GraphData *gd = nullptr;
+    double eps = 0, delta = 0;
+    uint64_t seed = 0;
+    int64_t N = 1024;
+    int nframes = 1;
+    int64_t probe_min = -1;
+    int64_t omega = 0;
+    double L = 0;
+    // device buffers
+    int32_t *counts = nullptr;
+    int32_t *frames = nullptr;  // [2][nframes][n]
+    size_t frames_len = 0;
+    double *scores = nullptr;
+    int cslot = -1;             // control block index in the runner
+    // progress
+    int64_t k = 0;              // epochs whose samplers were launched
+    int64_t merged = 0;         // epochs whose merges were launched
+    int64_t lo = 0;             // first sample of epoch k + 1
+    bool spec = false;          // epoch k's sampler was queued speculatively
+    bool done = false;
     int status = KADABRA_OK;
-    double ms_kernels = 0.0;
-    for (;;) {
-        ++k;
-        const int64_t hi = std::min<int64_t>(k * N, omega);  // k*N cannot overflow: N, k < 2^31
-        const int par = (int)(k & 1);
-        if (!next_launched) {
-            sa.lo = lo;
-            sa.hi = hi;
-            sa.parity = par;
-            sa.gate = -1;  // the host knows the previous boundary did not stop
-            HIP_OR_FAIL(hipEventRecord(g->ev_ks[par], s));
-            HIP_OR_FAIL(kd::launch_sample(team, (int)slots, sa, s));
-            HIP_OR_FAIL(hipEventRecord(g->ev_ke[par], s));
+    std::vector<int8_t> decisions;
+    int64_t tau = 0;
+    int decision = 0;
+    int64_t work[kd::ST_COUNT] = {};
+    double ms_kernels = 0.0;    // sampler launches that did this query's work
+    int64_t launches = 0;
+    std::chrono::steady_clock::time_point t_submit, t_done;
+
+    int64_t bound(int64_t epoch) const { return std::min<int64_t>(epoch * N, omega); }
+    ~Query()
+    {
+        dev_free(counts);
+        dev_free(frames);
+        dev_free(scores);
+    }
+};
+
+// The device engine shared by the queries of one handle or batch.
+struct Runner {
+    hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;
+    int num_cu = 0;
+    // sample slot pool
+    kd::SlotState st{};
+    int team = 0;
+    int64_t slots = 0;
+    unsigned long long *d_claim = nullptr;
+    uint64_t claim_next = 0;
+    bool pool_dirty = true;
+    // control blocks (one per concurrent query) and their pinned mirror
+    kd::Control *d_ctl = nullptr;
+    kd::Control *h_ctl = nullptr;
+    int ctl_cap = 0;
+    std::vector<int> free_cslots;
+    // launch tables: a ring of device tables and pinned staging copies
+    static constexpr int RING = 8;
+    int table_cap = 0;
+    kd::QueryDesc *d_qt[RING] = {};
+    kd::QueryDesc *h_qt[RING] = {};
+    kd::MergeDesc *d_mt[RING] = {};
+    kd::MergeDesc *h_mt[RING] = {};
+    int ring_pos = 0;
+    hipEvent_t ev_round = nullptr;
+    std::vector<hipEvent_t> ev_pool;
+    std::atomic<int> cancel{0};
+
+    ~Runner()
+    {
+        (void)hipStreamSynchronize(stream);
+        release_pool();
+        dev_release(d_claim);
+        dev_release(d_ctl);
+        if (h_ctl) (void)hipHostFree(h_ctl);
+        for (int r = 0; r < RING; ++r) {
+            dev_free(d_qt[r]);
+            dev_free(d_mt[r]);
+            if (h_qt[r]) (void)hipHostFree(h_qt[r]);
+            if (h_mt[r]) (void)hipHostFree(h_mt[r]);
         }
-        ca.tau = hi;
-        ca.parity = par;
-        ca.do_check = hi < omega;
-        HIP_OR_FAIL(kd::launch_merge_check(ca, s));
-        HIP_OR_FAIL(hipMemcpyAsync(&g->h_flags[par], &g->d_ctl->viol[par], sizeof(int32_t),
-                                   hipMemcpyDeviceToHost, s));
-        HIP_OR_FAIL(hipEventRecord(g->ev_flag[par], s));
-        next_launched = false;
-        if (g->overlap && hi < omega) {
-            // speculative: the next epoch's samples, discarded if this epoch stops
-            sa.lo = hi;
-            sa.hi = std::min<int64_t>((k + 1) * N, omega);
-            sa.parity = par ^ 1;
-            sa.gate = par;  // exits at once if this boundary's check stops the run
-            HIP_OR_FAIL(hipEventRecord(g->ev_ks[par ^ 1], s));
-            HIP_OR_FAIL(kd::launch_sample(team, (int)slots, sa, s));
-            HIP_OR_FAIL(hipEventRecord(g->ev_ke[par ^ 1], s));
-            next_launched = true;
+        if (ev_round) (void)hipEventDestroy(ev_round);
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+        if (own_stream) (void)hipStreamDestroy(own_stream);
+    }
+
+    int init()
+    {
+        hipError_t e;
+        int dev = 0;
+        if ((e = hipGetDevice(&dev)) != hipSuccess)
+            return fail(KADABRA_EDEVICE, "no HIP device: %s", hipGetErrorString(e));
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) num_cu = prop.multiProcessorCount;
+        HIP_OR_FAIL(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
+        stream = own_stream;
+        HIP_OR_FAIL(hipEventCreate(&ev_round));
+        HIP_OR_FAIL(alloc_n(&d_claim, 1));
+        HIP_OR_FAIL(hipMemcpy(d_claim, &claim_next, sizeof claim_next, hipMemcpyHostToDevice));
+        return KADABRA_OK;
+    }
+
+    void release_pool()
+    {
+        dev_release(st.code);
+        dev_release(st.sigma);
+        dev_release(st.ball);
+        dev_release(st.meet);
+        dev_release(st.meetw);
+        dev_release(st.loff);
+        st = kd::SlotState{};
+        team = 0;
+        slots = 0;
+        pool_dirty = true;
+    }
+
+    // A pool of `sl` slots for graphs of up to nstride vertices and lcap levels.
+    int ensure_pool(int tm, int64_t sl, int64_t nstride, int32_t lcap, int64_t *fc)
+    {
+        if (st.code && team == tm && slots == sl && st.nstride >= nstride && st.lcap >= lcap)
+            return KADABRA_OK;
+        release_pool();
+        const size_t S = (size_t)sl, ns = (size_t)nstride;
+        const int32_t cs = code_stride_for(nstride);
+        HIP_OR_FAIL(alloc_n(&st.code, S * (size_t)cs, fc));
+        HIP_OR_FAIL(alloc_n(&st.sigma, S * 2 * ns, fc));
+        HIP_OR_FAIL(alloc_n(&st.ball, S * 2 * ns, fc));
+        HIP_OR_FAIL(alloc_n(&st.meet, S * ns, fc));
+        HIP_OR_FAIL(alloc_n(&st.meetw, S * ns, fc));
+        HIP_OR_FAIL(alloc_n(&st.loff, S * 2 * (size_t)lcap, fc));
+        st.nstride = nstride;
+        st.lcap = lcap;
+        st.code_stride = cs;
+        team = tm;
+        slots = sl;
+        pool_dirty = true;
+        return KADABRA_OK;
+    }
+
+    int clear_pool_if_dirty()
+    {
+        if (!pool_dirty) return KADABRA_OK;
+        HIP_OR_FAIL(kd::launch_fill_u32(st.code, (size_t)slots * st.code_stride, 0u, stream));
+        HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)st.sigma, (size_t)slots * st.nstride * 8, 0u, stream));
+        pool_dirty = false;
+        return KADABRA_OK;
+    }
+
+    int ensure_tables(int cap, int64_t *fc)
+    {
+        if (cap <= table_cap && cap <= ctl_cap) return KADABRA_OK;
+        HIP_OR_FAIL(hipStreamSynchronize(stream));
+        const int ncap = std::max({cap, 2 * table_cap, 1});
+        for (int r = 0; r < RING; ++r) {
+            dev_release(d_qt[r]);
+            dev_release(d_mt[r]);
+            if (h_qt[r]) (void)hipHostFree(h_qt[r]);
+            if (h_mt[r]) (void)hipHostFree(h_mt[r]);
+            h_qt[r] = nullptr;
+            h_mt[r] = nullptr;
+            HIP_OR_FAIL(alloc_n(&d_qt[r], (size_t)ncap, fc));
+            HIP_OR_FAIL(alloc_n(&d_mt[r], (size_t)ncap, fc));
+            HIP_OR_FAIL(hipHostMalloc((void **)&h_qt[r], (size_t)ncap * sizeof(kd::QueryDesc), hipHostMallocDefault));
+            HIP_OR_FAIL(hipHostMalloc((void **)&h_mt[r], (size_t)ncap * sizeof(kd::MergeDesc), hipHostMallocDefault));
         }
-        HIP_OR_FAIL(hipEventSynchronize(g->ev_flag[par]));
-        {
-            float kms = 0.f;  // this epoch's sampling launch has finished
-            HIP_OR_FAIL(hipEventElapsedTime(&kms, g->ev_ks[par], g->ev_ke[par]));
-            ms_kernels += kms;
+        table_cap = ncap;
+        if (ncap > ctl_cap) {
+            // control blocks move: only while no query holds one
+            if (ctl_cap > 0 && (int)free_cslots.size() != ctl_cap)
+                return fail(KADABRA_ESTATE, "control blocks in use");
+            dev_release(d_ctl);
+            if (h_ctl) (void)hipHostFree(h_ctl);
+            h_ctl = nullptr;
+            HIP_OR_FAIL(alloc_n(&d_ctl, (size_t)ncap, fc));
+            HIP_OR_FAIL(hipHostMalloc((void **)&h_ctl, (size_t)ncap * sizeof(kd::Control), hipHostMallocDefault));
+            ctl_cap = ncap;
+            free_cslots.clear();
+            for (int c = ncap - 1; c >= 0; --c) free_cslots.push_back(c);
         }
-        tau = hi;
-        lo = hi;
-        if (hi == omega) {
-            decision = 2;
-        } else if (g->h_flags[par] == 0) {
-            decision = 1;
+        return KADABRA_OK;
+    }
+
+    hipEvent_t event(size_t i)
+    {
+        while (ev_pool.size() <= i) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            ev_pool.push_back(e);
         }
-        g->decisions.push_back((int8_t)decision);
-        if (decision) break;
-        if (g->cancel.load()) {
-            status = fail(KADABRA_ECANCELED, "run canceled at %lld samples", (long long)tau);
+        return ev_pool[i];
+    }
+
+    // Mapping for a set of queries (never changes a result).
+    void choose_mapping(const Params &p, int64_t nmax, int32_t lcap, int *tm, int64_t *sl) const
+    {
+        int t = p.team ? p.team : 256;
+        int64_t s = p.slots;
+        if (s == 0) {
+            s = (int64_t)std::max(num_cu, 1) * ((t == 64) ? 8 : 4);
+            size_t free_b = 0, total_b = 0;
+            if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0) {
+                const int64_t fit = (int64_t)((free_b / 2) / slot_bytes(nmax, lcap));
+                s = std::min(s, std::max<int64_t>(fit, 1));
+            }
+        }
+        *tm = t;
+        *sl = std::max<int64_t>(s, 1);
+    }
+
+    int start_query(Query &q, int64_t *fc);
+    void finish_query(Query &q);
+    int run(std::vector<Query *> &queries, const Params &p,
+            const std::function<void(std::vector<Query *> &)> &admit = nullptr,
+            int64_t sample_cap = -1, int64_t *fail_countdown = nullptr);
+};
+
+int Runner::start_query(Query &q, int64_t *fc)
+{
+    const size_t n = (size_t)q.gd->n;
+    if (!q.counts) HIP_OR_FAIL(alloc_n(&q.counts, n, fc));
+    if (q.frames_len != 2 * (size_t)q.nframes * n) {
+        dev_release(q.frames);
+        q.frames_len = 0;
+        HIP_OR_FAIL(alloc_n(&q.frames, 2 * (size_t)q.nframes * n, fc));
+        q.frames_len = 2 * (size_t)q.nframes * n;
+    }
+    if (free_cslots.empty()) return fail(KADABRA_ESTATE, "no free control block");
+    q.cslot = free_cslots.back();
+    free_cslots.pop_back();
+    HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)q.counts, n, 0u, stream));
+    HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)q.frames, 2 * (size_t)q.nframes * n, 0u, stream));
+    HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)(d_ctl + q.cslot), sizeof(kd::Control) / 4, 0u, stream));
+    q.k = q.merged = q.lo = 0;
+    q.spec = false;
+    q.done = false;
+    q.status = KADABRA_OK;
+    q.decisions.clear();
+    q.tau = 0;
+    q.decision = 0;
+    q.ms_kernels = 0.0;
+    q.launches = 0;
+    for (auto &w : q.work) w = 0;
+    return KADABRA_OK;
+}
+
+void Runner::finish_query(Query &q)
+{
+    q.done = true;
+    q.t_done = std::chrono::steady_clock::now();
+    if (q.cslot >= 0) {
+        free_cslots.push_back(q.cslot);
+        q.cslot = -1;
+    }
+}
+
+// The round loop (see the file header).  `admit` may append new queries at
+// every round (continuous batching); sample_cap >= 0 stops every query after
+// that many samples without checks (autotuning trials).
+int Runner::run(std::vector<Query *> &queries, const Params &p,
+                const std::function<void(std::vector<Query *> &)> &admit, int64_t sample_cap,
+                int64_t *fail_countdown)
+{
+    cancel.store(0);
+    std::vector<Query *> active;
+    auto take_new = [&](std::vector<Query *> &incoming) -> int {
+        for (Query *q : incoming) {
+            OK_OR_RETURN(start_query(*q, fail_countdown));
+            active.push_back(q);
+        }
+        incoming.clear();
+        return KADABRA_OK;
+    };
+    {
+        std::vector<Query *> first = queries;
+        OK_OR_RETURN(take_new(first));
+    }
+    OK_OR_RETURN(clear_pool_if_dirty());
+    // a sampler launch and the queries (with epochs) it carried, for timing
+    struct Launch {
+        hipEvent_t e0, e1;
+        std::vector<std::pair<Query *, int64_t>> items;
+    };
+    std::vector<Launch> launches;
+    size_t ev_next = 0;
+
+    auto launch_sampler = [&](std::vector<Query *> &qs, bool speculative) -> int {
+        if (qs.empty()) return KADABRA_OK;
+        const int r = ring_pos;
+        ring_pos = (ring_pos + 1) % RING;
+        kd::QueryDesc *h = h_qt[r];
+        int64_t total = 0;
+        Launch L;
+        for (size_t x = 0; x < qs.size(); ++x) {
+            Query &q = *qs[x];
+            const int64_t epoch = q.k + 1;
+            int64_t hi = q.bound(epoch);
+            if (sample_cap >= 0) hi = std::min(hi, sample_cap);
+            kd::QueryDesc &d = h[x];
+            d.row_ptr = q.gd->d_row_ptr;
+            d.col = q.gd->d_col;
+            d.comp = q.gd->d_comp;
+            d.parity = (int32_t)(epoch & 1);
+            d.frames = q.frames + (size_t)d.parity * q.nframes * (size_t)q.gd->n;
+            d.ctl = d_ctl + q.cslot;
+            d.seed = q.seed;
+            d.lo = q.lo;
+            d.hi = hi;
+            d.claim_begin = total;
+            d.probe_min = q.probe_min;
+            d.num_arcs = q.gd->arcs;
+            d.n = q.gd->n;
+            d.nframes = q.nframes;
+            d.gate = speculative ? (int32_t)(q.k & 1) : -1;
+            total += hi - q.lo;
+            q.k = epoch;
+            q.lo = hi;
+            q.spec = speculative;
+            L.items.push_back({&q, epoch});
+        }
+        HIP_OR_FAIL(hipMemcpyAsync(d_qt[r], h, qs.size() * sizeof(kd::QueryDesc), hipMemcpyHostToDevice, stream));
+        kd::SampleArgs sa{};
+        sa.q = d_qt[r];
+        sa.nq = (int32_t)qs.size();
+        sa.total = total;
+        sa.claim = d_claim;
+        sa.claim_base = claim_next;
+        sa.st = st;
+        claim_next += (uint64_t)total + (uint64_t)slots;  // every block makes one failing claim
+        const bool timed = launches.size() < 65536;  // time at most this many launches
+        if (timed) {
+            L.e0 = event(ev_next++);
+            L.e1 = event(ev_next++);
+            if (!L.e0 || !L.e1) return fail(KADABRA_EDEVICE, "event creation failed");
+            HIP_OR_FAIL(hipEventRecord(L.e0, stream));
+        }
+        HIP_OR_FAIL(kd::launch_sample(team, (int)slots, sa, stream));
+        if (timed) {
+            HIP_OR_FAIL(hipEventRecord(L.e1, stream));
+            launches.push_back(std::move(L));
+        }
+        return KADABRA_OK;
+    };
+
+    auto launch_merge = [&](std::vector<Query *> &qs) -> int {
+        if (qs.empty()) return KADABRA_OK;
+        const int r = ring_pos;
+        ring_pos = (ring_pos + 1) % RING;
+        kd::MergeDesc *h = h_mt[r];
+        int32_t blocks = 0;
+        for (size_t x = 0; x < qs.size(); ++x) {
+            Query &q = *qs[x];
+            const int64_t epoch = q.k;  // its sampler has been launched
+            kd::MergeDesc &m = h[x];
+            m.counts = q.counts;
+            m.parity = (int32_t)(epoch & 1);
+            m.frames = q.frames + (size_t)m.parity * q.nframes * (size_t)q.gd->n;
+            m.ctl = d_ctl + q.cslot;
+            m.tau = q.lo;
+            m.omega = q.omega;
+            m.L = q.L;
+            m.eps = q.eps;
+            m.n = q.gd->n;
+            m.nframes = q.nframes;
+            m.gate = -1;  // the host knows the previous boundary continued
+            m.do_check = (sample_cap < 0 && q.lo < q.omega) ? 1 : 0;
+            m.block_begin = blocks;
+            blocks += kd::merge_blocks_for(q.gd->n);
+            q.merged = epoch;
+        }
+        HIP_OR_FAIL(hipMemcpyAsync(d_mt[r], h, qs.size() * sizeof(kd::MergeDesc), hipMemcpyHostToDevice, stream));
+        kd::MergeArgs ma{};
+        ma.m = d_mt[r];
+        ma.nq = (int32_t)qs.size();
+        ma.nblocks = blocks;
+        HIP_OR_FAIL(kd::launch_merge_check(ma, stream));
+        return KADABRA_OK;
+    };
+
+    int status = KADABRA_OK;
+    while (!active.empty()) {
+        // samplers for queries whose next epoch is not queued yet
+        std::vector<Query *> fresh;
+        for (Query *q : active)
+            if (q->merged == q->k) fresh.push_back(q);
+        OK_OR_RETURN(launch_sampler(fresh, false));
+        OK_OR_RETURN(launch_merge(active));
+        HIP_OR_FAIL(hipMemcpyAsync(h_ctl, d_ctl, (size_t)ctl_cap * sizeof(kd::Control), hipMemcpyDeviceToHost, stream));
+        HIP_OR_FAIL(hipEventRecord(ev_round, stream));
+        // speculative next epoch for queries that may continue
+        std::vector<Query *> spec;
+        if (p.overlap)
+            for (Query *q : active) {
+                const bool capped = sample_cap >= 0 && q->lo >= sample_cap;
+                if (q->lo < q->omega && !capped) spec.push_back(q);
+            }
+        OK_OR_RETURN(launch_sampler(spec, true));
+        HIP_OR_FAIL(hipEventSynchronize(ev_round));
+        // decisions of this round's boundaries
+        std::vector<Query *> still;
+        for (Query *q : active) {
+            const kd::Control &c = h_ctl[q->cslot];
+            const int64_t tau = q->bound(q->merged);
+            const bool capped = sample_cap >= 0 && std::min(tau, sample_cap) >= sample_cap;
+            int dec = 0;
+            if (c.err) {
+                q->status = fail(KADABRA_EDEVICE, "device-side invariant failure in the sampler");
+                status = q->status;
+                pool_dirty = true;
+            } else if (capped) {
+                dec = 2;
+            } else if (tau == q->omega) {
+                dec = 2;
+            } else if (c.viol[q->merged & 1] == 0) {
+                dec = 1;
+            }
+            q->tau = std::min(tau, sample_cap >= 0 ? sample_cap : tau);
+            q->decisions.push_back((int8_t)dec);
+            if (dec || q->status != KADABRA_OK) {
+                q->decision = dec;
+                for (int w = 0; w < kd::ST_COUNT; ++w) q->work[w] = c.stats_total[w];
+                finish_query(*q);
+            } else {
+                still.push_back(q);
+            }
+        }
+        if (status != KADABRA_OK) break;
+        if (cancel.load()) {
+            for (Query *q : still) {
+                q->status = fail(KADABRA_ECANCELED, "run canceled at %lld samples", (long long)q->tau);
+                finish_query(*q);
+            }
+            status = KADABRA_ECANCELED;
             break;
         }
+        active.swap(still);
+        if (admit) {
+            std::vector<Query *> incoming;
+            admit(incoming);
+            OK_OR_RETURN(take_new(incoming));
+        }
     }
-    HIP_OR_FAIL(hipEventRecord(g->ev_stop, s));
-    kd::Control ctl;
-    HIP_OR_FAIL(hipMemcpyAsync(&ctl, g->d_ctl, sizeof ctl, hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(stream));
+    // sampler time of the launches that carried an epoch a query used
+    for (Launch &L : launches) {
+        float ms = 0.f;
+        HIP_OR_FAIL(hipEventElapsedTime(&ms, L.e0, L.e1));
+        for (auto &it : L.items) {
+            Query *q = it.first;
+            const size_t used = q->decisions.size();  // epochs 1 .. used were merged
+            if (it.second <= (int64_t)used) {
+                q->ms_kernels += ms / (double)L.items.size();
+                q->launches += 1;
+            }
+        }
+    }
+    return status;
+}
+
+}  // namespace
+
+struct kadabra_graph {
+    GraphData gd;
+    Params params;
+    Runner runner;
+    Query q;  // the last run
+    bool have_result = false;
+    double ms_total = 0.0;
+};
+
+struct kadabra_batch {
+    Params params;
+    Runner runner;
+    std::vector<std::unique_ptr<Query>> queries;
+    bool have_result = false;
+    double ms_total = 0.0;
+};
+
+namespace {
+
+int make_query(Query &q, const GraphData &gd, const Params &p, double eps, double delta, uint64_t seed,
+               int64_t N)
+{
+    if (!(eps > 0.0 && eps < 1.0)) return fail(KADABRA_EINVAL, "eps must be in (0, 1)");
+    if (!(delta > 0.0 && delta < 1.0)) return fail(KADABRA_EINVAL, "delta must be in (0, 1)");
+    if (N < 1 || N > INT32_MAX) return fail(KADABRA_EINVAL, "check_interval must be in [1, 2^31)");
+    const int64_t omega = omega_of(gd.vd, eps, delta);
+    if (omega > kMaxOmega || omega < 1)
+        return fail(KADABRA_ERANGE, "omega = %lld samples exceeds the int32 counters", (long long)omega);
+    q.gd = &gd;
+    q.eps = eps;
+    q.delta = delta;
+    q.seed = seed;
+    q.N = N;
+    q.nframes = p.frames;
+    q.probe_min = p.probe_min;
+    q.omega = omega;
+    q.L = std::log(4.0 * (double)gd.n / delta);
+    q.t_submit = std::chrono::steady_clock::now();
+    return KADABRA_OK;
+}
+
+// Runs queries (all on graphs of up to nmax vertices) to completion.
+int run_queries(Runner &R, std::vector<Query *> &qs, Params &p, int64_t sample_cap = -1)
+{
+    int64_t nmax = 1;
+    int32_t lcap = 3;
+    for (Query *q : qs) {
+        nmax = std::max<int64_t>(nmax, q->gd->n);
+        lcap = std::max(lcap, q->gd->vd + 2);  // a side reaches at most diameter <= VD - 1 levels
+    }
+    int tm;
+    int64_t sl;
+    R.choose_mapping(p, nmax, lcap, &tm, &sl);
+    int64_t *fc = &p.fail_alloc;
+    OK_OR_RETURN(R.ensure_pool(tm, sl, nmax, lcap, fc));
+    OK_OR_RETURN(R.ensure_tables((int)qs.size(), fc));
+    return R.run(qs, p, nullptr, sample_cap, fc);
+}
+
+void fill_stats(const Query &q, double ms_total, kadabra_stats *stats)
+{
+    memset(stats, 0, sizeof *stats);
+    stats->tau = q.tau;
+    stats->omega = q.omega;
+    stats->vd_bound = q.gd->vd;
+    stats->epochs = (int64_t)q.decisions.size();
+    stats->decision = q.decision;
+    stats->v_exp = q.work[kd::ST_VEXP];
+    stats->e_scan = q.work[kd::ST_ESCAN];
+    stats->e_bt = q.work[kd::ST_EBT];
+    stats->path_interior = q.work[kd::ST_INTERIOR];
+    stats->disconnected = q.work[kd::ST_DISCONN];
+    stats->log_inv_delta = q.L;
+    stats->ms_sampling = q.ms_kernels;
+    stats->ms_total = ms_total;
+    stats->ms_sample_kernels = q.ms_kernels;
+    stats->sample_launches = q.launches;
+}
+
+int read_result(const Query &q, hipStream_t s, double *scores, int32_t *counts)
+{
+    Query &mq = const_cast<Query &>(q);
+    const size_t n = (size_t)q.gd->n;
+    if (scores) {
+        if (!mq.scores) HIP_OR_FAIL(alloc_n(&mq.scores, n));
+        HIP_OR_FAIL(kd::launch_scores(q.counts, mq.scores, q.gd->n, q.tau, s));
+        HIP_OR_FAIL(hipMemcpyAsync(scores, mq.scores, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    if (counts) HIP_OR_FAIL(hipMemcpyAsync(counts, q.counts, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(hipStreamSynchronize(s));
-    if (ctl.err) {
-        g->state_dirty = true;
-        return fail(KADABRA_EDEVICE, "device-side invariant failure in the sampler");
+    return KADABRA_OK;
+}
+
+}  // namespace
+
+namespace {
+
+int ensure_graph_query(kadabra_graph *g, double eps, double delta, uint64_t seed)
+{
+    return make_query(g->q, g->gd, g->params, eps, delta, seed, g->params.check_interval);
+}
+
+// Trial-times mapping candidates on the first trial_samples samples of every
+// query (no stop checks) and keeps the fastest in *p.  Results never depend on
+// the mapping, so the choice cannot change any output.
+int autotune(Runner &R, std::vector<Query *> &qs, Params &p, int64_t trial_samples)
+{
+    struct Cand {
+        int team;
+        int64_t slots_mul2;  // slots = auto * mul2 / 2
+        int64_t probe;
+    };
+    const Cand cands[] = {{256, 2, -1}, {256, 4, -1}, {256, 1, -1}, {64, 2, -1}, {64, 4, -1},
+                          {256, 2, (int64_t)1 << 62}, {64, 4, (int64_t)1 << 62}};
+    const Params base = p;
+    double best = 1e300;
+    Params best_p = p;
+    for (const Cand &c : cands) {
+        Params t = base;
+        t.team = c.team;
+        t.probe_min = c.probe;
+        int tm;
+        int64_t sl;
+        int64_t nmax = 1;
+        int32_t lcap = 3;
+        for (Query *q : qs) {
+            nmax = std::max<int64_t>(nmax, q->gd->n);
+            lcap = std::max(lcap, q->gd->vd + 2);
+            q->probe_min = c.probe;
+        }
+        t.slots = 0;
+        R.choose_mapping(t, nmax, lcap, &tm, &sl);
+        t.slots = std::max<int64_t>(1, sl * c.slots_mul2 / 2);
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+            (size_t)t.slots * slot_bytes(nmax, lcap) > free_b / 2)
+            continue;
+        OK_OR_RETURN(run_queries(R, qs, t, trial_samples));  // warm-up: buffers, caches
+        const auto t0 = std::chrono::steady_clock::now();
+        OK_OR_RETURN(run_queries(R, qs, t, trial_samples));
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (ms < best) {
+            best = ms;
+            best_p = t;
+        }
     }
-    if (status != KADABRA_OK) return status;
-    float ms = 0.f;
-    HIP_OR_FAIL(hipEventElapsedTime(&ms, g->ev_start, g->ev_flag[(int)(k & 1)]));
-    g->ms_sampling = ms;
-    g->ms_kernels = ms_kernels;
-    g->tau = tau;
-    g->omega = omega;
-    g->epochs = k;
-    g->decision = decision;
-    g->L = L;
-    for (int q = 0; q < kd::ST_COUNT; ++q) g->work[q] = ctl.stats_total[q];
-    g->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_wall0).count();
-    g->have_result = true;
+    p.team = best_p.team;
+    p.slots = best_p.slots;
+    p.probe_min = best_p.probe_min;
+    for (Query *q : qs) q->probe_min = p.probe_min;
     return KADABRA_OK;
 }
 
@@ -449,7 +900,7 @@ extern "C" {
 
 const char *kadabra_last_error(void) { return g_last_error.c_str(); }
 
-int kadabra_version(void) { return 10000; }
+int kadabra_version(void) { return 10100; }
 
 int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr, const int32_t *col_idx,
                          kadabra_graph **out)
@@ -458,95 +909,50 @@ int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr, co
     if (!out) return fail(KADABRA_EINVAL, "out is NULL");
     *out = nullptr;
     int32_t max_deg = 0;
-    if (int rc = validate_csr(n, num_arcs, row_ptr, col_idx, &max_deg)) return rc;
-    kadabra_graph *g = new (std::nothrow) kadabra_graph;
+    OK_OR_RETURN(validate_csr(n, num_arcs, row_ptr, col_idx, &max_deg));
+    std::unique_ptr<kadabra_graph> g(new (std::nothrow) kadabra_graph);
     if (!g) return fail(KADABRA_ENOMEM, "host allocation failed");
-    g->n = n;
-    g->arcs = num_arcs;
-    g->max_deg = max_deg;
+    GraphData &gd = g->gd;
+    gd.n = n;
+    gd.arcs = num_arcs;
+    gd.max_deg = max_deg;
     std::vector<int32_t> comp;
-    preprocess(n, row_ptr, col_idx, comp, &g->ncomp, &g->vd);
-    auto bail = [&](int rc) {
-        delete g;
-        return rc;
-    };
-    hipError_t e = hipGetDevice(&g->device);
-    if (e != hipSuccess) return bail(fail(KADABRA_EDEVICE, "no HIP device: %s", hipGetErrorString(e)));
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) g->num_cu = prop.multiProcessorCount;
-    if ((e = hipStreamCreateWithFlags(&g->own_stream, hipStreamNonBlocking)) != hipSuccess)
-        return bail(fail(KADABRA_EDEVICE, "stream: %s", hipGetErrorString(e)));
-    g->stream = g->own_stream;
-    for (hipEvent_t *ev : {&g->ev_start, &g->ev_stop, &g->ev_flag[0], &g->ev_flag[1], &g->ev_ks[0],
-                           &g->ev_ks[1], &g->ev_ke[0], &g->ev_ke[1]})
-        if ((e = hipEventCreate(ev)) != hipSuccess)
-            return bail(fail(KADABRA_EDEVICE, "event: %s", hipGetErrorString(e)));
-    if ((e = hipHostMalloc((void **)&g->h_flags, 2 * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess)
-        return bail(fail(KADABRA_ENOMEM, "pinned host memory: %s", hipGetErrorString(e)));
+    preprocess(n, row_ptr, col_idx, comp, &gd.ncomp, &gd.vd);
+    OK_OR_RETURN(g->runner.init());
     struct {
         int32_t **dst;
         const int32_t *src;
         size_t count;
-    } up[] = {{&g->d_row_ptr, row_ptr, (size_t)n + 1},
-              {&g->d_col, col_idx, (size_t)num_arcs},
-              {&g->d_comp, comp.data(), (size_t)n}};
+    } up[] = {{&gd.d_row_ptr, row_ptr, (size_t)n + 1},
+              {&gd.d_col, col_idx, (size_t)num_arcs},
+              {&gd.d_comp, comp.data(), (size_t)n}};
     for (auto &u : up) {
-        if ((e = dev_alloc((void **)u.dst, u.count * sizeof(int32_t))) != hipSuccess)
-            return bail(fail(e == hipErrorOutOfMemory ? KADABRA_ENOMEM : KADABRA_EDEVICE,
-                             "device allocation: %s", hipGetErrorString(e)));
-        if (u.count &&
-            (e = hipMemcpy(*u.dst, u.src, u.count * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
-            return bail(fail(KADABRA_EDEVICE, "upload: %s", hipGetErrorString(e)));
+        HIP_OR_FAIL(alloc_n(u.dst, u.count));
+        if (u.count) HIP_OR_FAIL(hipMemcpy(*u.dst, u.src, u.count * sizeof(int32_t), hipMemcpyHostToDevice));
     }
-    *out = g;
+    *out = g.release();
     return KADABRA_OK;
 }
 
 int kadabra_set_param(kadabra_graph *g, const char *key, int64_t value)
 {
     if (!g || !key) return fail(KADABRA_EINVAL, "null argument");
-    if (!strcmp(key, "check_interval")) {
-        if (value < 1 || value > INT32_MAX) return fail(KADABRA_EINVAL, "check_interval must be in [1, 2^31)");
-        g->check_interval = value;
-    } else if (!strcmp(key, "team")) {
-        if (value != 0 && value != 64 && value != 256) return fail(KADABRA_EINVAL, "team must be 0, 64 or 256");
-        g->team = (int)value;
-    } else if (!strcmp(key, "slots")) {
-        if (value < 0 || value > (1 << 20)) return fail(KADABRA_EINVAL, "slots must be in [0, 2^20]");
-        g->slots = value;
-    } else if (!strcmp(key, "frames")) {
-        if (value < 1 || value > 4096) return fail(KADABRA_EINVAL, "frames must be in [1, 4096]");
-        g->frames = (int)value;
-    } else if (!strcmp(key, "overlap")) {
-        if (value != 0 && value != 1) return fail(KADABRA_EINVAL, "overlap must be 0 or 1");
-        g->overlap = (int)value;
-    } else if (!strcmp(key, "probe_min")) {
-        if (value < -1) return fail(KADABRA_EINVAL, "probe_min must be >= -1");
-        g->probe_min = value;
-    } else if (!strcmp(key, "test_fail_alloc")) {
-        if (value < 0) return fail(KADABRA_EINVAL, "test_fail_alloc must be >= 0");
-        g->fail_alloc = value;
-        g->release_run_buffers();  // the next run allocates afresh
-    } else {
-        return fail(KADABRA_EINVAL, "unknown parameter '%s'", key);
-    }
+    bool known;
+    OK_OR_RETURN(set_common_param(g->params, key, value, &known));
+    if (!known) return fail(KADABRA_EINVAL, "unknown parameter '%s'", key);
+    if (!strcmp(key, "test_fail_alloc")) g->runner.release_pool();  // the next run allocates afresh
     return KADABRA_OK;
 }
 
 int kadabra_get_param(const kadabra_graph *g, const char *key, int64_t *value)
 {
     if (!g || !key || !value) return fail(KADABRA_EINVAL, "null argument");
-    if (!strcmp(key, "check_interval")) *value = g->check_interval;
-    else if (!strcmp(key, "team")) *value = g->team;
-    else if (!strcmp(key, "slots")) *value = g->slots;
-    else if (!strcmp(key, "frames")) *value = g->frames;
-    else if (!strcmp(key, "overlap")) *value = g->overlap;
-    else if (!strcmp(key, "probe_min")) *value = g->probe_min;
-    else if (!strcmp(key, "vd_bound")) *value = g->vd;
-    else if (!strcmp(key, "components")) *value = g->ncomp;
-    else if (!strcmp(key, "max_degree")) *value = g->max_deg;
-    else if (!strcmp(key, "last_team")) *value = g->rb_team;
-    else if (!strcmp(key, "last_slots")) *value = g->rb_slots;
+    if (get_common_param(g->params, key, value) == 0) return KADABRA_OK;
+    if (!strcmp(key, "vd_bound")) *value = g->gd.vd;
+    else if (!strcmp(key, "components")) *value = g->gd.ncomp;
+    else if (!strcmp(key, "max_degree")) *value = g->gd.max_deg;
+    else if (!strcmp(key, "last_team")) *value = g->runner.team;
+    else if (!strcmp(key, "last_slots")) *value = g->runner.slots;
     else return fail(KADABRA_EINVAL, "unknown parameter '%s'", key);
     return KADABRA_OK;
 }
@@ -554,7 +960,7 @@ int kadabra_get_param(const kadabra_graph *g, const char *key, int64_t *value)
 int kadabra_set_stream(kadabra_graph *g, void *hip_stream)
 {
     if (!g) return fail(KADABRA_EINVAL, "null handle");
-    g->stream = hip_stream ? (hipStream_t)hip_stream : g->own_stream;
+    g->runner.stream = hip_stream ? (hipStream_t)hip_stream : g->runner.own_stream;
     return KADABRA_OK;
 }
 
@@ -562,41 +968,34 @@ int kadabra_run(kadabra_graph *g, double eps, double delta, uint64_t seed)
 {
     if (!g) return fail(KADABRA_EINVAL, "null handle");
     g_last_error.clear();
-    return run_impl(g, eps, delta, seed);
+    const auto t0 = std::chrono::steady_clock::now();
+    g->have_result = false;
+    OK_OR_RETURN(ensure_graph_query(g, eps, delta, seed));
+    std::vector<Query *> qs{&g->q};
+    OK_OR_RETURN(run_queries(g->runner, qs, g->params));
+    if (g->q.status != KADABRA_OK) return g->q.status;
+    g->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    g->have_result = true;
+    return KADABRA_OK;
+}
+
+int kadabra_autotune(kadabra_graph *g, double eps, double delta, int64_t trial_samples)
+{
+    if (!g) return fail(KADABRA_EINVAL, "null handle");
+    if (trial_samples < 1) return fail(KADABRA_EINVAL, "trial_samples must be >= 1");
+    g_last_error.clear();
+    g->have_result = false;
+    OK_OR_RETURN(ensure_graph_query(g, eps, delta, 0x5EEDull));
+    std::vector<Query *> qs{&g->q};
+    return autotune(g->runner, qs, g->params, trial_samples);
 }
 
 int kadabra_get_scores(const kadabra_graph *g, double *scores, int32_t *counts, kadabra_stats *stats)
 {
     if (!g) return fail(KADABRA_EINVAL, "null handle");
     if (!g->have_result) return fail(KADABRA_ESTATE, "no completed run");
-    kadabra_graph *mg = const_cast<kadabra_graph *>(g);
-    const size_t n = (size_t)g->n;
-    if (scores) {
-        if (!mg->d_scores) HIP_OR_FAIL(dev_alloc((void **)&mg->d_scores, n * sizeof(double)));
-        HIP_OR_FAIL(kd::launch_scores(g->d_counts, mg->d_scores, g->n, g->tau, g->stream));
-        HIP_OR_FAIL(hipMemcpyAsync(scores, mg->d_scores, n * sizeof(double), hipMemcpyDeviceToHost, g->stream));
-    }
-    if (counts)
-        HIP_OR_FAIL(hipMemcpyAsync(counts, g->d_counts, n * sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
-    HIP_OR_FAIL(hipStreamSynchronize(g->stream));
-    if (stats) {
-        memset(stats, 0, sizeof *stats);
-        stats->tau = g->tau;
-        stats->omega = g->omega;
-        stats->vd_bound = g->vd;
-        stats->epochs = g->epochs;
-        stats->decision = g->decision;
-        stats->v_exp = g->work[kd::ST_VEXP];
-        stats->e_scan = g->work[kd::ST_ESCAN];
-        stats->e_bt = g->work[kd::ST_EBT];
-        stats->path_interior = g->work[kd::ST_INTERIOR];
-        stats->disconnected = g->work[kd::ST_DISCONN];
-        stats->log_inv_delta = g->L;
-        stats->ms_sampling = g->ms_sampling;
-        stats->ms_total = g->ms_total;
-        stats->ms_sample_kernels = g->ms_kernels;
-        stats->sample_launches = g->epochs;
-    }
+    OK_OR_RETURN(read_result(g->q, g->runner.stream, scores, counts));
+    if (stats) fill_stats(g->q, g->ms_total, stats);
     return KADABRA_OK;
 }
 
@@ -604,10 +1003,10 @@ int kadabra_get_scores_device(const kadabra_graph *g, double *scores_dev, int32_
 {
     if (!g) return fail(KADABRA_EINVAL, "null handle");
     if (!g->have_result) return fail(KADABRA_ESTATE, "no completed run");
-    if (scores_dev) HIP_OR_FAIL(kd::launch_scores(g->d_counts, scores_dev, g->n, g->tau, g->stream));
+    if (scores_dev) HIP_OR_FAIL(kd::launch_scores(g->q.counts, scores_dev, g->gd.n, g->q.tau, g->runner.stream));
     if (counts_dev)
-        HIP_OR_FAIL(hipMemcpyAsync(counts_dev, g->d_counts, (size_t)g->n * sizeof(int32_t),
-                                   hipMemcpyDeviceToDevice, g->stream));
+        HIP_OR_FAIL(hipMemcpyAsync(counts_dev, g->q.counts, (size_t)g->gd.n * sizeof(int32_t),
+                                   hipMemcpyDeviceToDevice, g->runner.stream));
     return KADABRA_OK;
 }
 
@@ -615,9 +1014,9 @@ int kadabra_get_decisions(const kadabra_graph *g, int8_t *out, int64_t cap, int6
 {
     if (!g) return fail(KADABRA_EINVAL, "null handle");
     if (!g->have_result) return fail(KADABRA_ESTATE, "no completed run");
-    const int64_t m = (int64_t)g->decisions.size();
+    const int64_t m = (int64_t)g->q.decisions.size();
     if (out)
-        for (int64_t q = 0; q < std::min(cap, m); ++q) out[q] = g->decisions[(size_t)q];
+        for (int64_t k = 0; k < std::min(cap, m); ++k) out[k] = g->q.decisions[(size_t)k];
     if (count) *count = m;
     return KADABRA_OK;
 }
@@ -635,9 +1034,8 @@ int kadabra_eval_stop_fg(int32_t n, const int32_t *counts, int64_t tau, int64_t 
     };
     hipError_t e;
     const size_t m = (size_t)n;
-    if ((e = dev_alloc((void **)&d_c, m * sizeof(int32_t))) != hipSuccess ||
-        (e = dev_alloc((void **)&d_f, m * sizeof(double))) != hipSuccess ||
-        (e = dev_alloc((void **)&d_g, m * sizeof(double))) != hipSuccess) {
+    if ((e = alloc_n(&d_c, m)) != hipSuccess || (e = alloc_n(&d_f, m)) != hipSuccess ||
+        (e = alloc_n(&d_g, m)) != hipSuccess) {
         cleanup();
         return fail(e == hipErrorOutOfMemory ? KADABRA_ENOMEM : KADABRA_EDEVICE, "device allocation: %s",
                     hipGetErrorString(e));
@@ -654,15 +1052,19 @@ int kadabra_eval_stop_fg(int32_t n, const int32_t *counts, int64_t tau, int64_t 
 }
 
 #ifdef KADABRA_PHASE_TIMERS
-// Phase-timer builds only: cycles per sampler phase summed over all launches
-// of the last run (0 pair, 1 expansion, 2 level bookkeeping, 3 meeting draw,
-// 4 backtracking, 5 clearing).
+// Phase-timer builds only: sampler cycles per phase of the handle's last run
+// (0 pair, 1 expansion, 2 level bookkeeping, 3 meeting draw, 4 backtracking,
+// 5 clearing), summed over its control blocks.
 int kadabra_debug_phase_cycles(const kadabra_graph *g, int64_t *out8)
 {
-    if (!g || !g->d_ctl || !out8) return fail(KADABRA_EINVAL, "bad argument");
-    kd::Control ctl;
-    HIP_OR_FAIL(hipMemcpy(&ctl, g->d_ctl, sizeof ctl, hipMemcpyDeviceToHost));
-    for (int k = 0; k < 8; ++k) out8[k] = ctl.phase_cycles[k];
+    if (!g || !g->runner.d_ctl || !out8) return fail(KADABRA_EINVAL, "bad argument");
+    std::vector<kd::Control> ctl((size_t)g->runner.ctl_cap);
+    HIP_OR_FAIL(hipStreamSynchronize(g->runner.stream));
+    HIP_OR_FAIL(hipMemcpy(ctl.data(), g->runner.d_ctl, ctl.size() * sizeof(kd::Control), hipMemcpyDeviceToHost));
+    for (int k = 0; k < 8; ++k) {
+        out8[k] = 0;
+        for (const kd::Control &c : ctl) out8[k] += c.phase_cycles[k];
+    }
     return KADABRA_OK;
 }
 #endif
@@ -670,15 +1072,122 @@ int kadabra_debug_phase_cycles(const kadabra_graph *g, int64_t *out8)
 int kadabra_cancel(kadabra_graph *g)
 {
     if (!g) return fail(KADABRA_EINVAL, "null handle");
-    g->cancel.store(1);
+    g->runner.cancel.store(1);
     return KADABRA_OK;
 }
 
-void kadabra_destroy_graph(kadabra_graph *g)
+void kadabra_destroy_graph(kadabra_graph *g) { delete g; }
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+
+int kadabra_batch_create(kadabra_batch **out)
 {
-    if (!g) return;
-    (void)hipStreamSynchronize(g->stream);
-    delete g;
+    g_last_error.clear();
+    if (!out) return fail(KADABRA_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::unique_ptr<kadabra_batch> b(new (std::nothrow) kadabra_batch);
+    if (!b) return fail(KADABRA_ENOMEM, "host allocation failed");
+    OK_OR_RETURN(b->runner.init());
+    *out = b.release();
+    return KADABRA_OK;
 }
+
+int kadabra_batch_set_param(kadabra_batch *b, const char *key, int64_t value)
+{
+    if (!b || !key) return fail(KADABRA_EINVAL, "null argument");
+    if (!strcmp(key, "check_interval")) return fail(KADABRA_EINVAL, "check_interval is set per query");
+    bool known;
+    OK_OR_RETURN(set_common_param(b->params, key, value, &known));
+    if (!known) return fail(KADABRA_EINVAL, "unknown parameter '%s'", key);
+    return KADABRA_OK;
+}
+
+int kadabra_batch_get_param(const kadabra_batch *b, const char *key, int64_t *value)
+{
+    if (!b || !key || !value) return fail(KADABRA_EINVAL, "null argument");
+    if (get_common_param(b->params, key, value) == 0) return KADABRA_OK;
+    if (!strcmp(key, "last_team")) *value = b->runner.team;
+    else if (!strcmp(key, "last_slots")) *value = b->runner.slots;
+    else if (!strcmp(key, "queries")) *value = (int64_t)b->queries.size();
+    else return fail(KADABRA_EINVAL, "unknown parameter '%s'", key);
+    return KADABRA_OK;
+}
+
+int kadabra_batch_set_stream(kadabra_batch *b, void *hip_stream)
+{
+    if (!b) return fail(KADABRA_EINVAL, "null handle");
+    b->runner.stream = hip_stream ? (hipStream_t)hip_stream : b->runner.own_stream;
+    return KADABRA_OK;
+}
+
+int kadabra_batch_add(kadabra_batch *b, const kadabra_graph *g, double eps, double delta, uint64_t seed,
+                      int64_t check_interval, int32_t *index)
+{
+    if (!b || !g) return fail(KADABRA_EINVAL, "null handle");
+    std::unique_ptr<Query> q(new (std::nothrow) Query);
+    if (!q) return fail(KADABRA_ENOMEM, "host allocation failed");
+    OK_OR_RETURN(make_query(*q, g->gd, b->params, eps, delta, seed, check_interval));
+    b->queries.push_back(std::move(q));
+    b->have_result = false;
+    if (index) *index = (int32_t)b->queries.size() - 1;
+    return KADABRA_OK;
+}
+
+int kadabra_batch_run(kadabra_batch *b)
+{
+    if (!b) return fail(KADABRA_EINVAL, "null handle");
+    if (b->queries.empty()) return fail(KADABRA_ESTATE, "empty batch");
+    g_last_error.clear();
+    const auto t0 = std::chrono::steady_clock::now();
+    b->have_result = false;
+    std::vector<Query *> qs;
+    for (auto &q : b->queries) {
+        q->nframes = b->params.frames;
+        q->probe_min = b->params.probe_min;
+        qs.push_back(q.get());
+    }
+    OK_OR_RETURN(run_queries(b->runner, qs, b->params));
+    for (Query *q : qs)
+        if (q->status != KADABRA_OK) return q->status;
+    b->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    b->have_result = true;
+    return KADABRA_OK;
+}
+
+int kadabra_batch_autotune(kadabra_batch *b, int64_t trial_samples)
+{
+    if (!b) return fail(KADABRA_EINVAL, "null handle");
+    if (b->queries.empty()) return fail(KADABRA_ESTATE, "empty batch");
+    if (trial_samples < 1) return fail(KADABRA_EINVAL, "trial_samples must be >= 1");
+    b->have_result = false;
+    std::vector<Query *> qs;
+    for (auto &q : b->queries) qs.push_back(q.get());
+    return autotune(b->runner, qs, b->params, trial_samples);
+}
+
+int kadabra_batch_get_scores(const kadabra_batch *b, int32_t index, double *scores, int32_t *counts,
+                             kadabra_stats *stats)
+{
+    if (!b) return fail(KADABRA_EINVAL, "null handle");
+    if (index < 0 || index >= (int32_t)b->queries.size()) return fail(KADABRA_EINVAL, "bad query index");
+    if (!b->have_result) return fail(KADABRA_ESTATE, "no completed run");
+    const Query &q = *b->queries[(size_t)index];
+    OK_OR_RETURN(read_result(q, b->runner.stream, scores, counts));
+    if (stats) fill_stats(q, b->ms_total, stats);
+    return KADABRA_OK;
+}
+
+int kadabra_batch_clear(kadabra_batch *b)
+{
+    if (!b) return fail(KADABRA_EINVAL, "null handle");
+    (void)hipStreamSynchronize(b->runner.stream);
+    b->queries.clear();
+    b->have_result = false;
+    return KADABRA_OK;
+}
+
+void kadabra_batch_destroy(kadabra_batch *b) { delete b; }
 
 }  // extern "C"

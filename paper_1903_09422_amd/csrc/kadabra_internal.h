@@ -23,9 +23,8 @@ enum StatIdx {
     ST_COUNT
 };
 
-// Device control block (one per handle).
+// Device control block of one adaptive run (one per query).
 struct Control {
-    uint32_t claim[2];               // sample claim counters, by epoch parity
     int32_t viol[2];                 // stopping-rule violations, by epoch parity
     int32_t err;                     // device-side invariant failure (0 = none)
     int32_t pad;
@@ -34,52 +33,74 @@ struct Control {
     int64_t phase_cycles[8];         // per-phase cycles (phase-timer builds only)
 };
 
-// Per-slot sampling state.  Between samples every code word and every sigma
-// is zero (each sample clears what it touched).
+// Per-slot sampling state (a pool shared by every query of a launch; a slot
+// holds one sample at a time).  Between samples every code word and every
+// sigma is zero (each sample clears what it touched).
 struct SlotState {
     uint32_t *code;     // [slots][code_stride] 2-bit level codes per side, 8 vertices a word
-    Sigma *sigma;       // [slots][2][n] sigma_s, sigma_t
-    int32_t *ball;      // [slots][2][n] vertices reached by each side, BFS order
-    int32_t *meet;      // [slots][n] meeting set
-    uint64_t *meetw;    // [slots][n] meeting weights (when the set exceeds LDS)
+    Sigma *sigma;       // [slots][2][nstride] sigma_s, sigma_t
+    int32_t *ball;      // [slots][2][nstride] vertices reached by each side, BFS order
+    int32_t *meet;      // [slots][nstride] meeting set
+    uint64_t *meetw;    // [slots][nstride] meeting weights (when the set exceeds LDS)
     int32_t *loff;      // [slots][2][lcap] start of each BFS level in ball
-    int32_t lcap;       // entries per side (diameter bound + 2)
-    int32_t code_stride;  // words per slot (ceil(n / 8), rounded up to 64 bytes)
+    int64_t nstride;    // vertex capacity of a slot (largest n of the launch)
+    int32_t lcap;       // level capacity per side (largest diameter bound + 2)
+    int32_t code_stride;  // words per slot (ceil(nstride / 8), rounded up to 64 bytes)
 };
 
-struct SampleArgs {
+// One query's epoch in a sampling launch.
+struct QueryDesc {
     const int32_t *row_ptr;
     const int32_t *col;
     const int32_t *comp;
+    int32_t *frames;      // this epoch's frame set: [nframes][n]
+    Control *ctl;
+    uint64_t seed;
+    int64_t lo, hi;       // sample indices of this epoch: [lo, hi)
+    int64_t claim_begin;  // launch-wide claim index of sample lo
+    int64_t probe_min;    // >= 0: probe expansions of at least this many arcs; -1: auto rule
+    int64_t num_arcs;
     int32_t n;
     int32_t nframes;
-    uint64_t seed;
-    int64_t lo, hi;   // sample indices of this epoch: [lo, hi)
-    int32_t parity;   // epoch parity (selects claim counter, frames, stats)
-    int64_t probe_min;  // >= 0: expansions of at least this many arcs probe for the meeting
-                        // first; -1: probe when D_X * D_Y >= num_arcs
-    int64_t num_arcs;
-    int32_t gate;     // -1, or the parity of the previous boundary: if its check
-                      // found no violation the run has stopped and this launch exits
-    int32_t *frames;  // [2][nframes][n]
-    Control *ctl;
+    int32_t parity;       // epoch parity (frames, stats, flag)
+    int32_t gate;         // -1, or the parity of the previous boundary: if its check found
+                          // no violation the run has stopped and this epoch does no work
+};
+
+struct SampleArgs {
+    const QueryDesc *q;   // queries of this launch, by increasing claim_begin
+    int32_t nq;
+    int32_t pad;
+    int64_t total;        // samples of this launch
+    unsigned long long *claim;  // monotone claim counter
+    uint64_t claim_base;  // its value when this launch starts
     SlotState st;
 };
 
-struct CheckArgs {
-    int32_t *counts;  // [n] counters of samples [0, tau)
-    int32_t *frames;  // [2][nframes][n]
+// One query's boundary in a merge-and-check launch.
+struct MergeDesc {
+    int32_t *counts;      // [n] counters of samples [0, tau)
+    int32_t *frames;      // the epoch's frame set: [nframes][n]
+    Control *ctl;
+    int64_t tau, omega;
+    double L, eps;
     int32_t n;
     int32_t nframes;
     int32_t parity;
-    int32_t do_check; // 0: merge only (tau == omega)
-    int64_t tau, omega;
-    double L, eps;
-    Control *ctl;
+    int32_t gate;         // as in QueryDesc: skip if the run stopped at the previous boundary
+    int32_t do_check;     // 0: merge only (tau == omega)
+    int32_t block_begin;  // first block of this query in the launch
+};
+
+struct MergeArgs {
+    const MergeDesc *m;
+    int32_t nq;
+    int32_t nblocks;
 };
 
 hipError_t launch_sample(int team, int slots, const SampleArgs &a, hipStream_t s);
-hipError_t launch_merge_check(const CheckArgs &a, hipStream_t s);
+hipError_t launch_merge_check(const MergeArgs &a, hipStream_t s);
+int32_t merge_blocks_for(int32_t n);
 hipError_t launch_scores(const int32_t *counts, double *scores, int32_t n, int64_t tau,
                          hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, size_t count, uint32_t value, hipStream_t s);

@@ -350,6 +350,16 @@ struct Team {
     }
 };
 
+// A value every lane holds equally (read from LDS after a barrier), made
+// scalar so that the compiler keeps what derives from it in scalar registers.
+__device__ __forceinline__ int32_t uniform_i32(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform_i64(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Wave-aggregated append: every active lane with `take` receives a distinct
 // slot index from the LDS counter *cnt (one LDS atomic per wavefront).
 __device__ __forceinline__ int wave_append(bool take, int32_t *cnt)
@@ -396,7 +406,9 @@ struct SampleShared {
     int32_t sv[Cap<TEAM>::STAGE];     // staged meeting vertices / candidates
     Sigma sw[Cap<TEAM>::STAGE];       // their weights
     uint64_t red[16];                 // team reduction scratch
-    int64_t sample;                   // claimed sample index
+    uint64_t acc[ST_COUNT];           // work counters of the query being served (lane 0)
+    int64_t claim;                    // claimed launch-wide sample index
+    int32_t query;                    // its query
     int32_t nnext, nmeet, pick, ncand;
 };
 
@@ -436,48 +448,93 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
     constexpr int STAGE = Cap<TEAM>::STAGE;
     __shared__ SampleShared<TEAM> sm;
     const int lane = threadIdx.x;
-    const size_t n = (size_t)a.n;
+    const size_t ns = (size_t)a.st.nstride;
     const size_t slot = blockIdx.x;
     uint32_t *const code = a.st.code + slot * (size_t)a.st.code_stride;
-    Sigma *const sig0 = a.st.sigma + (2 * slot) * n;
-    Sigma *const sig1 = a.st.sigma + (2 * slot + 1) * n;
-    int32_t *const ball0 = a.st.ball + (2 * slot) * n;
-    int32_t *const ball1 = a.st.ball + (2 * slot + 1) * n;
-    int32_t *const meet = a.st.meet + slot * n;
-    uint64_t *const meetw = a.st.meetw + slot * n;
+    Sigma *const sig0 = a.st.sigma + (2 * slot) * ns;
+    Sigma *const sig1 = a.st.sigma + (2 * slot + 1) * ns;
+    int32_t *const ball0 = a.st.ball + (2 * slot) * ns;
+    int32_t *const ball1 = a.st.ball + (2 * slot + 1) * ns;
+    int32_t *const meet = a.st.meet + slot * ns;
+    uint64_t *const meetw = a.st.meetw + slot * ns;
     int32_t *const loff0 = a.st.loff + (2 * slot) * (size_t)a.st.lcap;
     int32_t *const loff1 = loff0 + a.st.lcap;
-    int32_t *const frame =
-        a.frames + ((size_t)a.parity * a.nframes + (blockIdx.x % a.nframes)) * n;
-    const int32_t *const row_ptr = a.row_ptr;
-    const int32_t *const col = a.col;
 
-    // launched before the host has read the previous boundary's check: stream
-    // order has already run that check, so its flag decides
-    if (a.gate >= 0 && a.ctl->viol[a.gate] == 0) return;
+    // the flag this launch's boundaries will raise starts clear (it was last
+    // read two boundaries ago; this launch reads only the other parity)
+    if (blockIdx.x == 0)
+        for (int32_t k = lane; k < a.nq; k += TEAM) a.q[k].ctl->viol[a.q[k].parity] = 0;
 
 #ifdef KADABRA_PHASE_TIMERS
     uint64_t ph_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    Control *ph_ctl = nullptr;
 #endif
-    // lane-private work counters (summed over the team at exit)
-    uint64_t st_vexp = 0, st_escan = 0, st_ebt = 0, st_int = 0, st_disc = 0;
+    // work counters (lane 0) of the query being served, flushed when the
+    // workgroup moves to another query and at exit
+    Control *acc_ctl = nullptr;
+    int32_t acc_par = 0;
+    if (lane < ST_COUNT) sm.acc[lane] = 0;
+    auto flush = [&]() {
+        if (lane != 0 || !acc_ctl) return;
+        int64_t *stp = acc_ctl->stats[acc_par];
+        for (int k = 0; k < ST_COUNT; ++k) {
+            if (sm.acc[k]) atomicAdd((unsigned long long *)&stp[k], sm.acc[k]);
+            sm.acc[k] = 0;
+        }
+    };
 
     for (;;) {
         __syncthreads();
-        if (lane == 0) sm.sample = a.lo + (int64_t)atomicAdd(&a.ctl->claim[a.parity], 1u);
+        if (lane == 0) {
+            const int64_t j = (int64_t)(atomicAdd(a.claim, 1ull) - a.claim_base);
+            int32_t qi = 0;
+            if (j < a.total) {  // the query whose range holds claim j
+                int32_t lo = 0, hi = a.nq;
+                while (hi - lo > 1) {
+                    const int32_t mid = (lo + hi) >> 1;
+                    if (a.q[mid].claim_begin <= j) lo = mid; else hi = mid;
+                }
+                qi = lo;
+            }
+            sm.claim = j;
+            sm.query = qi;
+        }
         T::sync();
-        const int64_t i = sm.sample;
-        if (i >= a.hi) break;
+        const int64_t jc = uniform_i64(sm.claim);
+        if (jc >= a.total) break;
+        // the query's fields, once, into scalar registers
+        const QueryDesc *const qd = a.q + uniform_i32(sm.query);
+        Control *const qctl = qd->ctl;
+        const int32_t qpar = qd->parity, qgate = qd->gate;
+        // launched before the host has read the previous boundary's check:
+        // stream order has already run that check, so its flag decides
+        if (qgate >= 0 && qctl->viol[qgate] == 0) continue;
+        const int64_t i = qd->lo + (jc - qd->claim_begin);
+        const int32_t *const row_ptr = qd->row_ptr;
+        const int32_t *const col = qd->col;
+        const int32_t *const comp = qd->comp;
+        const int32_t nv = qd->n;
+        const uint64_t seed = qd->seed;
+        const int64_t probe_min = qd->probe_min, num_arcs = qd->num_arcs;
+        int32_t *const frame = qd->frames + (size_t)(blockIdx.x % qd->nframes) * (size_t)nv;
+        if (qctl != acc_ctl || qpar != acc_par) {
+            flush();
+            acc_ctl = qctl;
+            acc_par = qpar;
+        }
+#ifdef KADABRA_PHASE_TIMERS
+        ph_ctl = qctl;
+#endif
         PHASE_BEGIN();
 
         // -- pair: ordered, s != t, uniform (64-bit multiply-high mapping) --
         uint64_t u_t;
-        const uint64_t u_s = philox_u64(a.seed, (uint64_t)i, 0u, &u_t);
-        const int32_t s = (int32_t)__umul64hi(u_s, (uint64_t)a.n);
-        int32_t t = (int32_t)__umul64hi(u_t, (uint64_t)(a.n - 1));
+        const uint64_t u_s = philox_u64(seed, (uint64_t)i, 0u, &u_t);
+        const int32_t s = (int32_t)__umul64hi(u_s, (uint64_t)nv);
+        int32_t t = (int32_t)__umul64hi(u_t, (uint64_t)(nv - 1));
         t += (t >= s) ? 1 : 0;
-        if (a.comp[s] != a.comp[t]) {  // Appendix C.1: no search across components
-            st_disc += (lane == 0);
+        if (comp[s] != comp[t]) {  // Appendix C.1: no search across components
+            if (lane == 0) sm.acc[ST_DISCONN] += 1;
             continue;
         }
         PHASE_MARK(0);
@@ -527,13 +584,13 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
             // D_X D_Y >= 4 x (number of arcs), an arc landing on a vertex with
             // probability proportional to its degree.
             const int64_t dsy = X ? dsum0 : dsum1;
-            const bool want_probe = (a.probe_min >= 0) ? (dsx >= a.probe_min)
-                                                       : (dsx * dsy >= 4 * a.num_arcs);
+            const bool want_probe = (probe_min >= 0) ? (dsx >= probe_min)
+                                                     : (dsx * dsy >= 4 * num_arcs);
             const bool probe = !retry && want_probe && bitw128(X ? fmass1 : fmass0) <= SIGMA_BITS;
             if (lane == 0) {
                 if (!retry) {
-                    st_vexp += (uint64_t)(fhix - flox);
-                    st_escan += (uint64_t)dsx;
+                    sm.acc[ST_VEXP] += (uint64_t)(fhix - flox);
+                    sm.acc[ST_ESCAN] += (uint64_t)dsx;
                 }
                 sm.nnext = 0;
                 sm.nmeet = 0;
@@ -613,8 +670,8 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                 __syncthreads();
             }
             PHASE_MARK(1);
-            nN = sm.nnext;
-            nM = sm.nmeet;
+            nN = uniform_i32(sm.nnext);
+            nM = uniform_i32(sm.nmeet);
             if (probe && nM == 0) {  // no meeting on this level: expand it in full
                 retry = true;
                 continue;
@@ -691,7 +748,7 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                 pm = T::max_u256(pm, sm.red);
                 const int shp = max(0, bitw256(pm) - WEIGHT_BITS);
                 uint64_t tot = 0;
-                int32_t vmin = a.n, vmax = -1;
+                int32_t vmin = nv, vmax = -1;
                 for (int32_t k = lane; k < nM; k += TEAM) {
                     const int32_t w = meet[k];
                     const uint64_t wt =
@@ -709,7 +766,7 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                 tot = T::sum_u64(tot, sm.red);
                 // team min / max of the ids (as maxima of n - id and id + 1),
                 // needed by the binary search over ids only
-                uint64_t mn = (uint64_t)(uint32_t)(a.n - vmin), mx = (uint64_t)(uint32_t)(vmax + 1);
+                uint64_t mn = (uint64_t)(uint32_t)(nv - vmin), mx = (uint64_t)(uint32_t)(vmax + 1);
 #pragma unroll
                 for (int o = 32; o > 0; o >>= 1) {
                     mn = max(mn, (uint64_t)__shfl_xor(mn, o, 64));
@@ -729,7 +786,7 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                     __syncthreads();
                 }
                 T::sync();  // staged weights visible to the whole team
-                const uint64_t r = __umul64hi(philox_u64(a.seed, (uint64_t)i, 1u), tot);
+                const uint64_t r = __umul64hi(philox_u64(seed, (uint64_t)i, 1u), tot);
                 if (nM <= TEAM) {
                     // rank by scanning the staged set: the element whose
                     // ascending-id inclusive prefix first exceeds r
@@ -740,7 +797,7 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                     v = sm.pick;
                 } else {
                     // smallest id v whose inclusive prefix (ascending ids) exceeds r
-                    int32_t lo = a.n - (int32_t)mn, hi = (int32_t)mx - 1;
+                    int32_t lo = nv - (int32_t)mn, hi = (int32_t)mx - 1;
                     while (lo < hi) {
                         const int32_t mid = lo + ((hi - lo) >> 1);
                         uint64_t part = 0;
@@ -763,7 +820,7 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
             const int32_t dv1 = (X == 1) ? lvl1 + 1 : lvl1;
             if (lane == 0 && dv0 > 0 && dv1 > 0) {
                 atomicAdd(&frame[v], 1);
-                ++st_int;
+                sm.acc[ST_INTERIOR] += 1;
             }
             // -- backtrack towards s (side 0) and t (side 1) -------------------
             for (int side = 0; side < 2 && ok; ++side) {
@@ -777,7 +834,7 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                     // predecessors = x's neighbours on level dxv - 1 of this side
                     const int32_t llo = loffs[dxv - 1], lhi = loffs[dxv];
                     const uint32_t j = 2u * (uint32_t)dxv + (uint32_t)side;
-                    const uint64_t U = philox_u64(a.seed, (uint64_t)i, j);
+                    const uint64_t U = philox_u64(seed, (uint64_t)i, j);
                     if (lane == 0) {
                         sm.pick = -1;
                         sm.ncand = 0;
@@ -846,22 +903,22 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                         }
                     }
                     __syncthreads();
-                    x = sm.pick;
+                    x = uniform_i32(sm.pick);
                     __syncthreads();
                     if (x < 0) {  // no predecessor found: cannot happen on a BFS level
-                        if (lane == 0) atomicExch(&a.ctl->err, 2);
+                        if (lane == 0) atomicExch(&qctl->err, 2);
                         ok = false;
                         break;
                     }
                     if (lane == 0) {
-                        st_ebt += (uint64_t)deg;
+                        sm.acc[ST_EBT] += (uint64_t)deg;
                         atomicAdd(&frame[x], 1);
-                        ++st_int;
+                        sm.acc[ST_INTERIOR] += 1;
                     }
                 }
             }
         } else if (lane == 0) {
-            atomicExch(&a.ctl->err, 1);
+            atomicExch(&qctl->err, 1);
         }
         PHASE_MARK(4);
 
@@ -880,25 +937,13 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
         }
         PHASE_MARK(5);
     }
+    flush();
 
 #ifdef KADABRA_PHASE_TIMERS
-    if (lane == 0)
+    if (lane == 0 && ph_ctl)
         for (int k = 0; k < 8; ++k)
-            if (ph_acc[k]) atomicAdd((unsigned long long *)&a.ctl->phase_cycles[k], ph_acc[k]);
+            if (ph_acc[k]) atomicAdd((unsigned long long *)&ph_ctl->phase_cycles[k], ph_acc[k]);
 #endif
-    // -- work counters -----------------------------------------------------
-    uint64_t *red = sm.red;
-    const uint64_t v0 = T::sum_u64(st_vexp, red), v1 = T::sum_u64(st_escan, red),
-                   v4 = T::sum_u64(st_ebt, red), v5 = T::sum_u64(st_int, red),
-                   v6 = T::sum_u64(st_disc, red);
-    if (lane == 0) {
-        int64_t *stp = a.ctl->stats[a.parity];
-        if (v0) atomicAdd((unsigned long long *)&stp[ST_VEXP], v0);
-        if (v1) atomicAdd((unsigned long long *)&stp[ST_ESCAN], v1);
-        if (v4) atomicAdd((unsigned long long *)&stp[ST_EBT], v4);
-        if (v5) atomicAdd((unsigned long long *)&stp[ST_INTERIOR], v5);
-        if (v6) atomicAdd((unsigned long long *)&stp[ST_DISCONN], v6);
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -920,39 +965,50 @@ __device__ __forceinline__ void stop_fg(int32_t c, double t, double w, double L,
     *g = (L / t) * (ag + sqrt(ag * ag + q));
 }
 
-__global__ __launch_bounds__(256) void merge_check_kernel(CheckArgs a)
+constexpr int32_t MERGE_BLOCK = 256;
+constexpr int32_t MERGE_MAX_BLOCKS = 1024;  // per query
+
+// blocks a query's boundary gets in a merge launch
+int32_t merge_blocks_for(int32_t n)
 {
-    const size_t n = (size_t)a.n;
-    int32_t *const fr = a.frames + (size_t)a.parity * a.nframes * n;
-    const double t = (double)a.tau, w = (double)a.omega;
+    const int32_t b = (n + MERGE_BLOCK - 1) / MERGE_BLOCK;
+    return b < 1 ? 1 : (b > MERGE_MAX_BLOCKS ? MERGE_MAX_BLOCKS : b);
+}
+
+__global__ __launch_bounds__(MERGE_BLOCK) void merge_check_kernel(MergeArgs a)
+{
+    // the query whose block range holds this block
+    int32_t lo = 0, hi = a.nq;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (a.m[mid].block_begin <= (int32_t)blockIdx.x) lo = mid; else hi = mid;
+    }
+    const MergeDesc &M = a.m[lo];
+    const int32_t qb = (int32_t)blockIdx.x - M.block_begin;
+    const int32_t nb = ((lo + 1 < a.nq) ? a.m[lo + 1].block_begin : a.nblocks) - M.block_begin;
+    // the run stopped at the previous boundary: leave its counters as they are
+    if (M.gate >= 0 && M.ctl->viol[M.gate] == 0) return;
+    const size_t n = (size_t)M.n;
+    const double t = (double)M.tau, w = (double)M.omega;
     int viol = 0;
-    for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-         v += (size_t)gridDim.x * blockDim.x) {
-        int32_t c = a.counts[v];
-        for (int f = 0; f < a.nframes; ++f) {
-            c += fr[(size_t)f * n + v];
-            fr[(size_t)f * n + v] = 0;
+    for (size_t v = (size_t)qb * MERGE_BLOCK + threadIdx.x; v < n; v += (size_t)nb * MERGE_BLOCK) {
+        int32_t c = M.counts[v];
+        for (int f = 0; f < M.nframes; ++f) {
+            c += M.frames[(size_t)f * n + v];
+            M.frames[(size_t)f * n + v] = 0;
         }
-        a.counts[v] = c;
-        if (a.do_check) {
+        M.counts[v] = c;
+        if (M.do_check) {
             double fv, gv;
-            stop_fg(c, t, w, a.L, &fv, &gv);
-            if (!(fv <= a.eps) || !(gv <= a.eps)) viol = 1;
+            stop_fg(c, t, w, M.L, &fv, &gv);
+            if (!(fv <= M.eps) || !(gv <= M.eps)) viol = 1;
         }
     }
-    if (__syncthreads_or(viol) && threadIdx.x == 0) atomicOr(&a.ctl->viol[a.parity], 1);
-    if (blockIdx.x == 0) {
-        // fold the epoch's work counters into the totals; prepare the next
-        // epoch of the other parity (its claims and flag were last used two
-        // epochs ago, and that flag has been read)
-        if (threadIdx.x < ST_COUNT) {
-            a.ctl->stats_total[threadIdx.x] += a.ctl->stats[a.parity][threadIdx.x];
-            a.ctl->stats[a.parity][threadIdx.x] = 0;
-        }
-        if (threadIdx.x == 0) {
-            a.ctl->claim[a.parity ^ 1] = 0u;
-            a.ctl->viol[a.parity ^ 1] = 0;
-        }
+    if (__syncthreads_or(viol) && threadIdx.x == 0) atomicOr(&M.ctl->viol[M.parity], 1);
+    if (qb == 0 && threadIdx.x < ST_COUNT) {
+        // fold the epoch's work counters into the run's totals
+        M.ctl->stats_total[threadIdx.x] += M.ctl->stats[M.parity][threadIdx.x];
+        M.ctl->stats[M.parity][threadIdx.x] = 0;
     }
 }
 
@@ -997,9 +1053,10 @@ hipError_t launch_sample(int team, int slots, const SampleArgs &a, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_merge_check(const CheckArgs &a, hipStream_t s)
+hipError_t launch_merge_check(const MergeArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(merge_check_kernel, dim3(grid_for((size_t)a.n, 256)), dim3(256), 0, s, a);
+    if (a.nq == 0) return hipSuccess;
+    hipLaunchKernelGGL(merge_check_kernel, dim3(a.nblocks), dim3(MERGE_BLOCK), 0, s, a);
     return hipGetLastError();
 }
 

@@ -186,6 +186,110 @@ def perturbed_grid(side: int = 1024, delete_frac: float = 0.05, shortcut_frac: f
     return from_edges(n, eu, ev, lcc=lcc, name=f"pgrid_{side}_s{seed}")
 
 
+def _rhg_edges(r: np.ndarray, theta: np.ndarray, R: float, bands: int = 16):
+    """Pairs (i, j), i < j, of points at hyperbolic distance <= R, where
+    cosh d = cosh r_i cosh r_j - sinh r_i sinh r_j cos(theta_i - theta_j).
+    Candidates come from angular windows per radial band: for r_j >= b, the
+    largest angle that still connects shrinks as b grows, so the window at the
+    band's lower bound b holds every partner in that band."""
+    n = r.size
+    order = np.argsort(theta, kind="stable")
+    r, theta = r[order], theta[order]
+    ch, sh = np.cosh(r), np.sinh(r)
+    coshR = np.cosh(R)
+    edges_u, edges_v = [], []
+    bounds = np.linspace(0.0, R, bands + 1)
+    band_of = np.minimum(np.searchsorted(bounds, r, side="right") - 1, bands - 1)
+    two_pi = 2.0 * np.pi
+    for c in range(bands):
+        members = np.flatnonzero(band_of == c)  # sorted by angle already
+        if members.size == 0:
+            continue
+        ang_c = theta[members]
+        b = bounds[c]
+        chb, shb = np.cosh(b), np.sinh(b)
+        for i0 in range(0, n, 65536):
+            ii = np.arange(i0, min(n, i0 + 65536))
+            with np.errstate(divide="ignore", invalid="ignore"):
+                arg = (ch[ii] * chb - coshR) / (sh[ii] * shb)
+            dmax = np.where(np.isfinite(arg), np.arccos(np.clip(arg, -1.0, 1.0)), np.pi)
+            dmax = np.where(arg <= -1.0, np.pi, dmax)
+            lo_a, hi_a = theta[ii] - dmax, theta[ii] + dmax
+            # the window, split where it wraps around 2 pi
+            parts = [(np.maximum(lo_a, 0.0), np.minimum(hi_a, two_pi)),
+                     (np.where(lo_a < 0.0, lo_a + two_pi, two_pi), np.full(ii.size, two_pi)),
+                     (np.zeros(ii.size), np.where(hi_a > two_pi, hi_a - two_pi, 0.0))]
+            for a, z in parts:
+                s0 = np.searchsorted(ang_c, a, side="left")
+                s1 = np.searchsorted(ang_c, z, side="right")
+                cnt = np.maximum(s1 - s0, 0)
+                tot = int(cnt.sum())
+                if tot == 0:
+                    continue
+                src = np.repeat(ii, cnt)
+                start = np.repeat(s0 - np.cumsum(cnt) + cnt, cnt)
+                dst = members[np.arange(tot) + start]
+                keep = src < dst
+                src, dst = src[keep], dst[keep]
+                cosd = ch[src] * ch[dst] - sh[src] * sh[dst] * np.cos(theta[src] - theta[dst])
+                ok = cosd <= coshR
+                edges_u.append(order[src[ok]])
+                edges_v.append(order[dst[ok]])
+    if not edges_u:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    return np.concatenate(edges_u), np.concatenate(edges_v)
+
+
+def rhg(n: int, mean_degree: float = 10.0, gamma: float = 2.8, seed: int = 1, *,
+        lcc: bool = True) -> CSR:
+    """Threshold random hyperbolic graph: n points on a hyperbolic disk of
+    radius R, angle uniform, radius density alpha sinh(alpha r) / (cosh(alpha R)
+    - 1) with alpha = (gamma - 1) / 2; vertices adjacent iff their hyperbolic
+    distance is at most R.  R is bisected until the mean degree is within 0.5
+    of mean_degree (the same points are reused for every R)."""
+    rng = np.random.default_rng(seed)
+    alpha = (gamma - 1.0) / 2.0
+    theta = rng.random(n) * 2.0 * np.pi
+    u = rng.random(n)
+
+    def build(R):
+        r = np.arccosh(1.0 + (np.cosh(alpha * R) - 1.0) * u) / alpha
+        return _rhg_edges(r, theta, R)
+
+    xi = alpha / (alpha - 0.5)
+    R = 2.0 * np.log(2.0 * xi * xi * n / (np.pi * mean_degree))  # asymptotic estimate
+    lo, hi = R - 4.0, R + 4.0
+    for _ in range(40):
+        eu, ev = build(R)
+        deg = 2.0 * eu.size / n
+        if abs(deg - mean_degree) <= 0.5:
+            break
+        if deg > mean_degree:
+            lo = R
+        else:
+            hi = R
+        R = 0.5 * (lo + hi)
+    return from_edges(n, eu, ev, lcc=lcc, name=f"rhg_n{n}_d{mean_degree:g}_s{seed}")
+
+
+def batch_pool(seed: int = 1):
+    """The batched workload: 64 graphs, 32 R-MAT of scale 12 + (k mod 5)
+    (edge factor 16) and 32 threshold random hyperbolic graphs of
+    n = 2^(14 + k mod 4), mean degree 10, power-law exponent 2.8; each query's
+    eps drawn from {0.05, 0.02, 0.01}; delta = 0.1, checks every 1024 samples.
+    Returns a list of (graph, eps, delta, check_interval, query_seed)."""
+    rng = np.random.default_rng(seed)
+    eps_choices = np.array([0.05, 0.02, 0.01])
+    out = []
+    for k in range(32):
+        g = rmat(12 + (k % 5), 16, seed=1000 + k)
+        out.append((g, float(eps_choices[rng.integers(3)]), 0.1, 1024, 1 + k))
+    for k in range(32):
+        g = rhg(1 << (14 + (k % 4)), 10.0, 2.8, seed=2000 + k)
+        out.append((g, float(eps_choices[rng.integers(3)]), 0.1, 1024, 33 + k))
+    return out
+
+
 # --------------------------------------------------------------------------
 # Small named graphs (closed forms and brute force)
 # --------------------------------------------------------------------------

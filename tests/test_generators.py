@@ -59,3 +59,27 @@ def test_generator_sizes():
     assert g.num_edges == e - round(0.05 * e) + round(0.001 * e)
     r = G.rmat(10, 8, seed=2, lcc=False)
     assert r.n == 1024 and r.num_edges <= 8 * 1024
+
+
+def test_rhg_matches_brute_force():
+    """The banded candidate search finds exactly the pairs at hyperbolic
+    distance <= R (all-pairs check on a small disk)."""
+    rng = np.random.default_rng(4)
+    n, alpha, R = 1500, 0.9, 11.0
+    theta = rng.random(n) * 2 * np.pi
+    r = np.arccosh(1.0 + (np.cosh(alpha * R) - 1.0) * rng.random(n)) / alpha
+    eu, ev = G._rhg_edges(r, theta, R)
+    got = set(zip(np.minimum(eu, ev).tolist(), np.maximum(eu, ev).tolist()))
+    i, j = np.triu_indices(n, 1)
+    cosd = np.cosh(r[i]) * np.cosh(r[j]) - np.sinh(r[i]) * np.sinh(r[j]) * np.cos(theta[i] - theta[j])
+    want = set(zip(i[cosd <= np.cosh(R)].tolist(), j[cosd <= np.cosh(R)].tolist()))
+    assert len(want) > 1000
+    assert got == want
+
+
+def test_rhg_mean_degree_and_shape():
+    g = G.rhg(1 << 14, 10.0, 2.8, seed=3, lcc=False)
+    check_canonical(g, connected=False)
+    assert abs(g.num_arcs / g.n - 10.0) <= 0.5
+    deg = g.degrees()
+    assert deg.max() > 20 * deg.mean()  # heavy-tailed
