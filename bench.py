@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 # Algorithmic bytes per unit of work counted by the sampler (a lower bound:
-# what any implementation of the method must read per unit; see DESIGN.md):
+# what any implementation of the method must read per unit):
 BYTES_PER = {
     "v_exp": 28,          # expanded frontier vertex: row_ptr pair 8 + sigma 16 + list entry 4
     "e_scan": 12,         # scanned arc: column index 4 + the neighbour's distance pair 8
@@ -60,7 +60,10 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat18",
-                    choices=["rmat18", "pgrid1024", "er4096", "batch64"])
+                    choices=["rmat18", "pgrid1024", "er4096", "batch64", "serve"])
+    ap.add_argument("--serve-queries", type=int, default=256)
+    ap.add_argument("--no-rmat22", action="store_true",
+                    help="serve: leave R-MAT scale 22 out of the graph pool")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--team", type=int, default=0)
     ap.add_argument("--slots", type=int, default=0)
@@ -91,12 +94,15 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": src.numel() * 4}))
         return 0
-    if args.gpus == 1 and args.workload == "batch64":
-        return bench_batch(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the sampling "
-              "path here is single-device; see DESIGN.md for how it would shard.", file=sys.stderr)
+              "path here runs on a single device.", file=sys.stderr)
         return 2
+
+    if args.workload == "batch64":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import torch
 
@@ -264,6 +270,100 @@ def bench_batch(args) -> int:
         "batch_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
     }
     batch.close()
+    for h in handles:
+        h.close()
+    print(json.dumps(out))
+    return 0
+
+
+def bench_serve(args) -> int:
+    """Serving: a seeded stream of queries (graph drawn uniformly from the
+    64-graph pool, the perturbed 1024 x 1024 grid and R-MAT scale 22; eps from
+    {0.05, 0.01}, delta 0.1, checks every 16384 samples) against resident
+    graphs.  Two servers answer the same stream: one that runs a query at a
+    time (max_active 1, first come first served) and the continuous-batching
+    one.  Each first takes the whole stream at once (saturation: its
+    capacity), then Poisson arrivals at 0.5, 0.8 and 1.0 times the one-at-a-
+    time capacity.  value = the batching server's samples/s at saturation."""
+    import torch
+
+    from paper_1903_09422_amd import Graph, Server, graphs
+
+    print("serve: building graphs", file=sys.stderr, flush=True)
+    pool = graphs.serve_pool(with_rmat22=not args.no_rmat22)
+    handles = [Graph.from_csr(g) for g in pool]
+    queries, gaps = graphs.serve_trace(len(pool), args.serve_queries, seed=7 + args.seed)
+    print(f"serve: {len(pool)} graphs, {len(queries)} queries", file=sys.stderr, flush=True)
+
+    def replay(srv, rate):
+        """Submit the stream (all at once if rate is None), wait for all;
+        returns (total samples, makespan s, server info)."""
+        srv.info(reset=True)
+        offsets = np.zeros(len(queries)) if rate is None else np.cumsum(gaps) / rate
+        t0 = time.perf_counter()
+        tickets = []
+        for (gi, eps, delta, n_check, seed), off in zip(queries, offsets):
+            now = time.perf_counter() - t0
+            if off > now:
+                time.sleep(off - now)
+            tickets.append((srv.submit(gi, eps, delta, seed, n_check), time.perf_counter() - t0))
+        tot, end = 0, 0.0
+        for (t, ts), (gi, *_rest) in zip(tickets, queries):
+            srv.wait(t)
+            res, lat = srv.result(t, gi, scores=False)
+            tot += res.tau
+            end = max(end, ts + lat / 1e3)
+            srv.release(t)
+        return tot, end, srv.info()
+
+    out_rates = {}
+    legs = {}
+    for name, max_active in (("one_at_a_time", 1), ("batching", 0)):
+        srv = Server(handles, max_active=max_active)
+        for k, v in (("team", args.team), ("slots", args.slots), ("probe_min", args.probe_min)):
+            srv.set_param(k, v)
+        replay(srv, None)  # warm-up: pool, buffers, code
+        torch.cuda.synchronize()
+        tot, span, info = replay(srv, None)
+        legs[name] = {"samples_per_s": tot / span, "queries_per_s": len(queries) / span,
+                      "makespan_s": span, "samples": tot,
+                      "p50_ms": info["p50_ms"], "p99_ms": info["p99_ms"],
+                      "peak_active": info["peak_active"]}
+        print(f"serve: {name} saturated {tot / span:.4g} samples/s", file=sys.stderr, flush=True)
+        cap = legs["one_at_a_time"]["queries_per_s"]
+        for f in (0.5, 0.8, 1.0):
+            t2, span2, inf2 = replay(srv, f * cap)
+            assert t2 == tot
+            out_rates.setdefault(f"{f:.1f}x", {"arrivals_per_s": f * cap})[name] = {
+                "p50_ms": inf2["p50_ms"], "p99_ms": inf2["p99_ms"], "max_ms": inf2["max_ms"],
+                "mean_queue_ms": inf2["mean_queue_ms"], "samples_per_s": t2 / span2,
+                "peak_active": inf2["peak_active"]}
+            print(f"serve: {name} at {f}x p50 {inf2['p50_ms']:.3g} ms p99 {inf2['p99_ms']:.3g} ms",
+                  file=sys.stderr, flush=True)
+        srv.close()
+    assert legs["one_at_a_time"]["samples"] == legs["batching"]["samples"]
+    b, o = legs["batching"], legs["one_at_a_time"]
+    out = {
+        "metric": "samples/s (KADABRA adaptive sampling, served stream at saturation)",
+        "value": b["samples_per_s"],
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": b["makespan_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"serve: {len(queries)} queries over {len(pool)} resident graphs "
+                               "(64-graph pool + perturbed grid 1024^2"
+                               + ("" if args.no_rmat22 else " + R-MAT scale 22") +
+                               "), eps from {0.05, 0.01}, delta 0.1, checks every 16384 samples"},
+        "saturated": legs,
+        "speedup_vs_one_at_a_time": b["samples_per_s"] / o["samples_per_s"],
+        "poisson": out_rates,
+    }
     for h in handles:
         h.close()
     print(json.dumps(out))

@@ -213,6 +213,85 @@ int kadabra_batch_get_scores(const kadabra_batch *b, int32_t index, double *scor
 int kadabra_batch_clear(kadabra_batch *b);
 void kadabra_batch_destroy(kadabra_batch *b);
 
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching.  A server owns a worker thread and one      */
+/* device engine over a fixed set of resident graphs.  Queries are submitted */
+/* at any time from any thread; at every round boundary (one sampling launch */
+/* plus one merge-and-check launch) the worker admits waiting queries, in    */
+/* submission order, while their device memory fits the server's budget,    */
+/* and they join the next sampling launch beside the queries in flight; a    */
+/* query leaves as soon as its own stopping rule fires.  Each query's result */
+/* is exactly the one kadabra_run gives for it alone (Algorithm 1 with the   */
+/* checks of Appendix C.2 depends on the query only, never on its company).  */
+/* ------------------------------------------------------------------------ */
+typedef struct kadabra_server kadabra_server;
+
+typedef struct {
+    int64_t submitted;     /* queries accepted by kadabra_server_submit */
+    int64_t completed;     /* finished (stop rule, omega, or error) */
+    int64_t failed;        /* of which ended with an error */
+    int64_t active;        /* admitted and sampling */
+    int64_t pending;       /* waiting for admission */
+    int64_t bytes_in_use;  /* device bytes held by admitted or unreleased queries */
+    int64_t budget_bytes;  /* admission budget */
+    int64_t peak_active;   /* most queries in one launch so far */
+    double p50_ms;         /* latency (submit to result final) percentiles over */
+    double p99_ms;         /* completed queries since creation or the last reset */
+    double max_ms;
+    double mean_queue_ms;  /* mean time from submit to admission */
+} kadabra_server_info;
+
+/*
+ * Creates a server over graphs[0 .. ngraphs) (handles from
+ * kadabra_create_graph; they must outlive the server and not be destroyed
+ * meanwhile; their own runs stay independent).  hbm_budget_bytes bounds the
+ * device memory of admitted queries (per query: counters 4n, score buffer 8n,
+ * and while sampling the epoch frames 8n * frames bytes); 0 takes half of the
+ * device memory free after the sample pool is sized.  max_active bounds the
+ * queries in one launch (0: 256).  Errors: EINVAL, ENOMEM, EDEVICE.
+ */
+int kadabra_server_create(const kadabra_graph *const *graphs, int32_t ngraphs, int64_t hbm_budget_bytes,
+                          int32_t max_active, kadabra_server **out);
+
+/* Mapping parameters as kadabra_batch_set_param; only before the first submit
+ * (ESTATE after).  get_param also reads "graphs", "max_active", "budget". */
+int kadabra_server_set_param(kadabra_server *s, const char *key, int64_t value);
+int kadabra_server_get_param(const kadabra_server *s, const char *key, int64_t *value);
+
+/*
+ * Enqueues a query on graph `graph_index` and returns its ticket (> 0) at
+ * once.  Errors: EINVAL (index or parameters), ERANGE (omega >= 2^31, or the
+ * query alone exceeds the budget), EDEVICE (the worker hit a device error).
+ */
+int kadabra_server_submit(kadabra_server *s, int32_t graph_index, double eps, double delta, uint64_t seed,
+                          int64_t check_interval, int64_t *ticket);
+
+/* Blocks until the ticket's query is final or timeout_s seconds pass
+ * (timeout_s < 0: no limit); *done = 1 if final.  Errors: EINVAL (ticket). */
+int kadabra_server_wait(kadabra_server *s, int64_t ticket, double timeout_s, int32_t *done);
+
+/*
+ * Reads a final query's scores (float64[n], counts / tau, computed on the
+ * device) and/or counters (int32[n]) into host buffers, its statistics (with
+ * ms_total = its latency from submit to final), and its latency.  Any
+ * pointer may be NULL.  Returns the query's own error if it failed.
+ * Errors: EINVAL (ticket), ESTATE (not final yet), the query's error.
+ */
+int kadabra_server_result(kadabra_server *s, int64_t ticket, double *scores, int32_t *counts,
+                          kadabra_stats *stats, double *latency_ms);
+
+/* Returns a final query's device memory to the server (the ticket becomes
+ * invalid).  Call it after the last kadabra_server_result on the ticket has
+ * returned.  Errors: EINVAL (ticket), ESTATE (not final yet). */
+int kadabra_server_release(kadabra_server *s, int64_t ticket);
+
+/* Counters and latency percentiles; reset = 1 restarts the latency window. */
+int kadabra_server_info_get(kadabra_server *s, kadabra_server_info *info, int32_t reset);
+
+/* Cancels waiting and running queries (ECANCELED), stops the worker, frees
+ * everything (NULL is a no-op). */
+void kadabra_server_destroy(kadabra_server *s);
+
 /* Asks a run in progress on another thread to stop at its next boundary
  * (kadabra_run then returns ECANCELED).  Safe to call concurrently. */
 int kadabra_cancel(kadabra_graph *g);

@@ -18,9 +18,9 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from ._lib import EXPORTS, KadabraError, Stats, check, lib  # noqa: F401
+from ._lib import EXPORTS, KadabraError, ServerInfo, Stats, check, lib  # noqa: F401
 
-__all__ = ["Graph", "Batch", "RunResult", "KadabraError", "eval_stop_fg", "lib"]
+__all__ = ["Graph", "Batch", "Server", "RunResult", "KadabraError", "eval_stop_fg", "lib"]
 
 
 @dataclass
@@ -195,6 +195,79 @@ class Batch:
     def close(self) -> None:
         if getattr(self, "_h", None):
             lib().kadabra_batch_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous batching over resident graphs: submit() returns a ticket at
+    once; a native worker admits waiting queries at every round boundary
+    while their device memory fits the budget.  Each result equals the
+    query's own Graph.run result."""
+
+    def __init__(self, graphs, hbm_budget_bytes: int = 0, max_active: int = 0):
+        self._graphs = list(graphs)  # the server references their device CSR
+        arr = (C.c_void_p * len(self._graphs))(*[g._h.value for g in self._graphs])
+        h = C.c_void_p()
+        check(lib().kadabra_server_create(arr, len(self._graphs), int(hbm_budget_bytes),
+                                          int(max_active), C.byref(h)))
+        self._h = h
+
+    def set_param(self, key: str, value: int) -> None:
+        check(lib().kadabra_server_set_param(self._h, key.encode(), int(value)))
+
+    def get_param(self, key: str) -> int:
+        v = C.c_int64()
+        check(lib().kadabra_server_get_param(self._h, key.encode(), C.byref(v)))
+        return int(v.value)
+
+    def submit(self, graph_index: int, eps: float, delta: float, seed: int,
+               check_interval: int) -> int:
+        t = C.c_int64()
+        check(lib().kadabra_server_submit(self._h, int(graph_index), float(eps), float(delta),
+                                          int(seed), int(check_interval), C.byref(t)))
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout: float = -1.0) -> bool:
+        done = C.c_int32()
+        check(lib().kadabra_server_wait(self._h, int(ticket), float(timeout), C.byref(done)))
+        return bool(done.value)
+
+    def result(self, ticket: int, graph_index: int, scores: bool = True):
+        """(RunResult, latency in ms) of a final query."""
+        n = self._graphs[graph_index].n
+        sc = np.empty(n, dtype=np.float64) if scores else None
+        counts = np.empty(n, dtype=np.int32)
+        st = Stats()
+        lat = C.c_double()
+        check(lib().kadabra_server_result(self._h, int(ticket),
+                                          sc.ctypes.data if sc is not None else None,
+                                          counts.ctypes.data, C.byref(st), C.byref(lat)))
+        return RunResult(tau=int(st.tau), counts=counts, scores=sc, stats=st.as_dict(),
+                         decisions=np.empty(0, dtype=np.int8)), float(lat.value)
+
+    def release(self, ticket: int) -> None:
+        check(lib().kadabra_server_release(self._h, int(ticket)))
+
+    def info(self, reset: bool = False) -> dict:
+        inf = ServerInfo()
+        check(lib().kadabra_server_info_get(self._h, C.byref(inf), 1 if reset else 0))
+        return inf.as_dict()
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().kadabra_server_destroy(self._h)
             self._h = None
 
     def __enter__(self):

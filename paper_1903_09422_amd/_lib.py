@@ -23,9 +23,13 @@ EXPORTS = (
     "kadabra_version", "kadabra_autotune", "kadabra_batch_create", "kadabra_batch_set_param",
     "kadabra_batch_get_param", "kadabra_batch_set_stream", "kadabra_batch_add", "kadabra_batch_run",
     "kadabra_batch_autotune", "kadabra_batch_get_scores", "kadabra_batch_clear",
-    "kadabra_batch_destroy",
+    "kadabra_batch_destroy", "kadabra_server_create", "kadabra_server_set_param",
+    "kadabra_server_get_param", "kadabra_server_submit", "kadabra_server_wait",
+    "kadabra_server_result", "kadabra_server_release", "kadabra_server_info_get",
+    "kadabra_server_destroy",
 )
-VOID_FUNCS = ("kadabra_destroy_graph", "kadabra_batch_destroy", "kadabra_last_error")
+VOID_FUNCS = ("kadabra_destroy_graph", "kadabra_batch_destroy", "kadabra_server_destroy",
+              "kadabra_last_error")
 
 
 class KadabraError(RuntimeError):
@@ -40,6 +44,16 @@ class Stats(C.Structure):
         "path_interior", "disconnected")] + [
         ("log_inv_delta", C.c_double), ("ms_sampling", C.c_double), ("ms_total", C.c_double),
         ("ms_sample_kernels", C.c_double), ("sample_launches", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in (
+        "submitted", "completed", "failed", "active", "pending", "bytes_in_use",
+        "budget_bytes", "peak_active")] + [
+        (k, C.c_double) for k in ("p50_ms", "p99_ms", "max_ms", "mean_queue_ms")]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -94,6 +108,18 @@ def lib() -> C.CDLL:
     L.kadabra_batch_clear.argtypes = [vp]
     L.kadabra_batch_destroy.argtypes = [vp]
     L.kadabra_batch_destroy.restype = None
+    L.kadabra_server_create.argtypes = [vp, C.c_int32, C.c_int64, C.c_int32, C.POINTER(vp)]
+    L.kadabra_server_set_param.argtypes = [vp, C.c_char_p, C.c_int64]
+    L.kadabra_server_get_param.argtypes = [vp, C.c_char_p, i64p]
+    L.kadabra_server_submit.argtypes = [vp, C.c_int32, C.c_double, C.c_double, C.c_uint64, C.c_int64,
+                                        i64p]
+    L.kadabra_server_wait.argtypes = [vp, C.c_int64, C.c_double, C.POINTER(C.c_int32)]
+    L.kadabra_server_result.argtypes = [vp, C.c_int64, vp, vp, C.POINTER(Stats),
+                                        C.POINTER(C.c_double)]
+    L.kadabra_server_release.argtypes = [vp, C.c_int64]
+    L.kadabra_server_info_get.argtypes = [vp, C.POINTER(ServerInfo), C.c_int32]
+    L.kadabra_server_destroy.argtypes = [vp]
+    L.kadabra_server_destroy.restype = None
     for name in EXPORTS:
         if name not in VOID_FUNCS:
             getattr(L, name).restype = C.c_int

@@ -17,6 +17,8 @@
 //               exactly samples [0, B_k) either way).
 //   kadabra_graph   one graph on the device, running one query at a time.
 //   kadabra_batch   many queries on many graphs in the same launches.
+//   kadabra_server  continuous batching: a worker thread runs the round loop
+//                   and admits submitted queries at every round boundary.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,8 +28,13 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
 #include <functional>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <memory>
 #include <new>
 #include <string>
@@ -346,7 +353,8 @@ struct Runner {
     kd::MergeDesc *h_mt[RING] = {};
     int ring_pos = 0;
     hipEvent_t ev_round = nullptr;
-    std::vector<hipEvent_t> ev_pool;
+    std::vector<hipEvent_t> ev_pool;   // every event created
+    std::vector<hipEvent_t> ev_free;   // those not recording a launch in flight
     std::atomic<int> cancel{0};
 
     ~Runner()
@@ -379,7 +387,10 @@ struct Runner {
         stream = own_stream;
         HIP_OR_FAIL(hipEventCreate(&ev_round));
         HIP_OR_FAIL(alloc_n(&d_claim, 1));
-        HIP_OR_FAIL(hipMemcpy(d_claim, &claim_next, sizeof claim_next, hipMemcpyHostToDevice));
+        // zeroed on the runner's stream and waited for: every later launch,
+        // on whichever stream, sees the counter at claim_next = 0
+        HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)d_claim, 2, 0u, own_stream));
+        HIP_OR_FAIL(hipStreamSynchronize(own_stream));
         return KADABRA_OK;
     }
 
@@ -463,17 +474,24 @@ struct Runner {
         return KADABRA_OK;
     }
 
-    hipEvent_t event(size_t i)
+    hipEvent_t take_event()
     {
-        while (ev_pool.size() <= i) {
-            hipEvent_t e = nullptr;
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
-            ev_pool.push_back(e);
+        if (!ev_free.empty()) {
+            hipEvent_t e = ev_free.back();
+            ev_free.pop_back();
+            return e;
         }
-        return ev_pool[i];
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        ev_pool.push_back(e);
+        return e;
     }
 
-    // Mapping for a set of queries (never changes a result).
+    size_t pool_bytes() const { return st.code ? (size_t)slots * slot_bytes(st.nstride, st.lcap) : 0; }
+
+    // Mapping for a set of queries (never changes a result).  The automatic
+    // slot count is capped at half of the device memory that is free or held
+    // by this runner's own pool, so repeated runs keep the same pool.
     void choose_mapping(const Params &p, int64_t nmax, int32_t lcap, int *tm, int64_t *sl) const
     {
         int t = p.team ? p.team : 256;
@@ -482,6 +500,7 @@ struct Runner {
             s = (int64_t)std::max(num_cu, 1) * ((t == 64) ? 8 : 4);
             size_t free_b = 0, total_b = 0;
             if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0) {
+                free_b += pool_bytes();
                 const int64_t fit = (int64_t)((free_b / 2) / slot_bytes(nmax, lcap));
                 s = std::min(s, std::max<int64_t>(fit, 1));
             }
@@ -492,9 +511,13 @@ struct Runner {
 
     int start_query(Query &q, int64_t *fc);
     void finish_query(Query &q);
+    // admit: may append new queries at every round (continuous batching);
+    // on_done: called for each query once its result is final and the runner
+    // holds no further reference to it.
     int run(std::vector<Query *> &queries, const Params &p,
             const std::function<void(std::vector<Query *> &)> &admit = nullptr,
-            int64_t sample_cap = -1, int64_t *fail_countdown = nullptr);
+            int64_t sample_cap = -1, int64_t *fail_countdown = nullptr,
+            const std::function<void(Query *)> &on_done = nullptr);
 };
 
 int Runner::start_query(Query &q, int64_t *fc)
@@ -541,7 +564,7 @@ void Runner::finish_query(Query &q)
 // that many samples without checks (autotuning trials).
 int Runner::run(std::vector<Query *> &queries, const Params &p,
                 const std::function<void(std::vector<Query *> &)> &admit, int64_t sample_cap,
-                int64_t *fail_countdown)
+                int64_t *fail_countdown, const std::function<void(Query *)> &on_done)
 {
     cancel.store(0);
     std::vector<Query *> active;
@@ -560,11 +583,25 @@ int Runner::run(std::vector<Query *> &queries, const Params &p,
     OK_OR_RETURN(clear_pool_if_dirty());
     // a sampler launch and the queries (with epochs) it carried, for timing
     struct Launch {
-        hipEvent_t e0, e1;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
         std::vector<std::pair<Query *, int64_t>> items;
     };
-    std::vector<Launch> launches;
-    size_t ev_next = 0;
+    std::deque<Launch> pend;  // launched, not yet accounted
+    // a finished launch's time goes to the queries whose merged epochs it carried
+    auto account = [&](Launch &L) -> int {
+        float ms = 0.f;
+        HIP_OR_FAIL(hipEventElapsedTime(&ms, L.e0, L.e1));
+        for (auto &it : L.items) {
+            Query *q = it.first;
+            if (q && it.second <= (int64_t)q->decisions.size()) {
+                q->ms_kernels += ms / (double)L.items.size();
+                q->launches += 1;
+            }
+        }
+        ev_free.push_back(L.e0);
+        ev_free.push_back(L.e1);
+        return KADABRA_OK;
+    };
 
     auto launch_sampler = [&](std::vector<Query *> &qs, bool speculative) -> int {
         if (qs.empty()) return KADABRA_OK;
@@ -609,18 +646,13 @@ int Runner::run(std::vector<Query *> &queries, const Params &p,
         sa.claim_base = claim_next;
         sa.st = st;
         claim_next += (uint64_t)total + (uint64_t)slots;  // every block makes one failing claim
-        const bool timed = launches.size() < 65536;  // time at most this many launches
-        if (timed) {
-            L.e0 = event(ev_next++);
-            L.e1 = event(ev_next++);
-            if (!L.e0 || !L.e1) return fail(KADABRA_EDEVICE, "event creation failed");
-            HIP_OR_FAIL(hipEventRecord(L.e0, stream));
-        }
+        L.e0 = take_event();
+        L.e1 = take_event();
+        if (!L.e0 || !L.e1) return fail(KADABRA_EDEVICE, "event creation failed");
+        HIP_OR_FAIL(hipEventRecord(L.e0, stream));
         HIP_OR_FAIL(kd::launch_sample(team, (int)slots, sa, stream));
-        if (timed) {
-            HIP_OR_FAIL(hipEventRecord(L.e1, stream));
-            launches.push_back(std::move(L));
-        }
+        HIP_OR_FAIL(hipEventRecord(L.e1, stream));
+        pend.push_back(std::move(L));
         return KADABRA_OK;
     };
 
@@ -677,16 +709,23 @@ int Runner::run(std::vector<Query *> &queries, const Params &p,
                 if (q->lo < q->omega && !capped) spec.push_back(q);
             }
         OK_OR_RETURN(launch_sampler(spec, true));
+        const size_t in_flight = spec.empty() ? 0 : 1;  // this round's speculative launch
         HIP_OR_FAIL(hipEventSynchronize(ev_round));
         // decisions of this round's boundaries
-        std::vector<Query *> still;
+        std::vector<Query *> still, finished;
         for (Query *q : active) {
             const kd::Control &c = h_ctl[q->cslot];
             const int64_t tau = q->bound(q->merged);
             const bool capped = sample_cap >= 0 && std::min(tau, sample_cap) >= sample_cap;
             int dec = 0;
             if (c.err) {
-                q->status = fail(KADABRA_EDEVICE, "device-side invariant failure in the sampler");
+                static const char *const site[] = {"?", "more BFS levels than the vertex-diameter bound",
+                                                   "no predecessor on a BFS level", "empty frontier"};
+                q->status = fail(KADABRA_EDEVICE,
+                                 "device-side invariant failure in the sampler (%s) at sample %lld of the "
+                                 "query with seed %llu on a graph of %d vertices",
+                                 site[(c.err >= 1 && c.err <= 3) ? c.err : 0], (long long)c.err_sample,
+                                 (unsigned long long)q->seed, q->gd->n);
                 status = q->status;
                 pool_dirty = true;
             } else if (capped) {
@@ -701,20 +740,38 @@ int Runner::run(std::vector<Query *> &queries, const Params &p,
             if (dec || q->status != KADABRA_OK) {
                 q->decision = dec;
                 for (int w = 0; w < kd::ST_COUNT; ++w) q->work[w] = c.stats_total[w];
-                finish_query(*q);
+                finished.push_back(q);
             } else {
                 still.push_back(q);
             }
         }
-        if (status != KADABRA_OK) break;
-        if (cancel.load()) {
+        // account the launches that have completed (all but this round's
+        // speculative one), drop finished queries from it, hand them over
+        while (pend.size() > in_flight) {
+            OK_OR_RETURN(account(pend.front()));
+            pend.pop_front();
+        }
+        if (cancel.load() && status == KADABRA_OK) {
             for (Query *q : still) {
                 q->status = fail(KADABRA_ECANCELED, "run canceled at %lld samples", (long long)q->tau);
-                finish_query(*q);
+                finished.push_back(q);
             }
+            still.clear();
             status = KADABRA_ECANCELED;
-            break;
         }
+        if (status != KADABRA_OK)
+            for (Query *q : still) {  // cut short by another query's failure
+                if (q->status == KADABRA_OK) q->status = status;
+                finished.push_back(q);
+            }
+        for (Query *q : finished) {
+            for (Launch &L : pend)
+                for (auto &it : L.items)
+                    if (it.first == q) it.first = nullptr;
+            finish_query(*q);
+            if (on_done) on_done(q);
+        }
+        if (status != KADABRA_OK) break;
         active.swap(still);
         if (admit) {
             std::vector<Query *> incoming;
@@ -723,18 +780,9 @@ int Runner::run(std::vector<Query *> &queries, const Params &p,
         }
     }
     HIP_OR_FAIL(hipStreamSynchronize(stream));
-    // sampler time of the launches that carried an epoch a query used
-    for (Launch &L : launches) {
-        float ms = 0.f;
-        HIP_OR_FAIL(hipEventElapsedTime(&ms, L.e0, L.e1));
-        for (auto &it : L.items) {
-            Query *q = it.first;
-            const size_t used = q->decisions.size();  // epochs 1 .. used were merged
-            if (it.second <= (int64_t)used) {
-                q->ms_kernels += ms / (double)L.items.size();
-                q->launches += 1;
-            }
-        }
+    while (!pend.empty()) {
+        OK_OR_RETURN(account(pend.front()));
+        pend.pop_front();
     }
     return status;
 }
@@ -756,6 +804,103 @@ struct kadabra_batch {
     std::vector<std::unique_ptr<Query>> queries;
     bool have_result = false;
     double ms_total = 0.0;
+};
+
+// A query submitted to a server: the run plus its ticket and budget charge.
+struct Served : Query {
+    int64_t ticket = 0;
+    int64_t charge = 0;        // budget bytes held now
+    int64_t frame_bytes = 0;   // part of the charge returned when sampling ends
+    bool admitted = false;
+    bool final_ = false;
+    std::string err;
+    std::chrono::steady_clock::time_point t_admit;
+    double latency_ms = 0.0;
+};
+
+struct kadabra_server {
+    Params params;
+    Runner runner;
+    std::vector<const GraphData *> graphs;
+    int64_t nmax = 1;
+    int32_t lcap = 3;
+    int64_t budget = 0;
+    int32_t max_active = 256;
+    int device = 0;
+    hipStream_t io = nullptr;  // result reads, beside the worker's stream
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Served *> pending;
+    std::unordered_map<int64_t, std::unique_ptr<Served>> tickets;
+    int64_t next_ticket = 1;
+    // device buffers of finished or released queries, by size, for reuse
+    std::unordered_map<size_t, std::vector<void *>> bins;
+    int64_t in_use = 0, binned = 0;
+    int64_t active = 0, peak_active = 0;
+    int64_t submitted = 0, completed = 0, failed = 0;
+    std::vector<double> lat;
+    double queue_ms_sum = 0.0;
+    int64_t queue_n = 0;
+    bool started = false, stop = false;
+    bool mapped = false;  // the pool matches params (fixed from the first run on)
+    int broken = KADABRA_OK;
+    std::string broken_err;
+    std::thread worker;
+
+    ~kadabra_server();
+    int64_t charge_of(const GraphData &g) const
+    {
+        return (int64_t)g.n * (4 + 8 + 8 * (int64_t)params.frames);
+    }
+    void *take_bin(size_t bytes)
+    {
+        auto it = bins.find(bytes);
+        if (it == bins.end() || it->second.empty()) return nullptr;
+        void *p = it->second.back();
+        it->second.pop_back();
+        binned -= (int64_t)bytes;
+        return p;
+    }
+    void put_bin(void *p, size_t bytes)
+    {
+        if (!p) return;
+        bins[bytes].push_back(p);
+        binned += (int64_t)bytes;
+    }
+    bool can_admit_locked() const
+    {
+        return !pending.empty() && active < max_active && in_use + pending.front()->charge <= budget;
+    }
+    // Moves admissible queries (in submission order) to out; buffers that no
+    // longer fit next to the admitted ones are handed back in to_free.
+    void admit_locked(std::vector<Query *> &out, std::vector<void *> &to_free)
+    {
+        while (can_admit_locked()) {
+            Served *v = pending.front();
+            pending.pop_front();
+            const size_t n = (size_t)v->gd->n;
+            v->admitted = true;
+            v->t_admit = std::chrono::steady_clock::now();
+            queue_ms_sum += std::chrono::duration<double, std::milli>(v->t_admit - v->t_submit).count();
+            queue_n += 1;
+            in_use += v->charge;
+            active += 1;
+            peak_active = std::max(peak_active, active);
+            v->counts = (int32_t *)take_bin(n * sizeof(int32_t));
+            const size_t fl = 2 * (size_t)v->nframes * n;
+            v->frames = (int32_t *)take_bin(fl * sizeof(int32_t));
+            v->frames_len = v->frames ? fl : 0;
+            v->scores = (double *)take_bin(n * sizeof(double));
+            out.push_back(v);
+        }
+        for (auto &b : bins) {
+            while (in_use + binned > budget && !b.second.empty()) {
+                to_free.push_back(b.second.back());
+                b.second.pop_back();
+                binned -= (int64_t)b.first;
+            }
+        }
+    }
 };
 
 namespace {
@@ -894,7 +1039,107 @@ int autotune(Runner &R, std::vector<Query *> &qs, Params &p, int64_t trial_sampl
     return KADABRA_OK;
 }
 
+// The server's worker: waits for submissions, then runs the round loop for
+// as long as any query is active, admitting new ones at every boundary.
+void server_main(kadabra_server *s)
+{
+    (void)hipSetDevice(s->device);
+    auto on_done = [s](Query *q) {
+        Served *v = static_cast<Served *>(q);
+        std::lock_guard<std::mutex> lk(s->mu);
+        v->final_ = true;
+        if (v->status != KADABRA_OK) {
+            v->err = g_last_error;
+            s->failed += 1;
+        }
+        v->latency_ms = std::chrono::duration<double, std::milli>(v->t_done - v->t_submit).count();
+        s->lat.push_back(v->latency_ms);
+        s->completed += 1;
+        s->active -= 1;
+        // the frames are free once the last merge has run (an epoch queued
+        // speculatively for this query exits on the device without writing)
+        s->put_bin(v->frames, v->frames_len * sizeof(int32_t));
+        v->frames = nullptr;
+        v->frames_len = 0;
+        s->in_use -= v->frame_bytes;
+        v->charge -= v->frame_bytes;
+        s->cv_done.notify_all();
+    };
+    auto admit = [s](std::vector<Query *> &incoming) {
+        std::vector<void *> to_free;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            if (s->stop) s->runner.cancel.store(1);
+            else s->admit_locked(incoming, to_free);
+        }
+        for (void *p : to_free) dev_free(p);
+    };
+    for (;;) {
+        std::vector<Query *> first;
+        std::vector<void *> to_free;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_work.wait(lk, [s] { return s->stop || s->can_admit_locked(); });
+            if (s->stop) break;
+            s->admit_locked(first, to_free);
+        }
+        for (void *p : to_free) dev_free(p);
+        int rc = KADABRA_OK;
+        if (!s->mapped) {
+            int tm;
+            int64_t sl;
+            s->runner.choose_mapping(s->params, s->nmax, s->lcap, &tm, &sl);
+            rc = s->runner.ensure_pool(tm, sl, s->nmax, s->lcap, nullptr);
+            s->mapped = rc == KADABRA_OK;
+        }
+        if (rc == KADABRA_OK) rc = s->runner.run(first, s->params, admit, -1, nullptr, on_done);
+        if (rc != KADABRA_OK && rc != KADABRA_ECANCELED) {
+            // a device failure: every query still admitted fails with it and
+            // the server accepts no more work
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->broken = rc;
+            s->broken_err = g_last_error;
+            for (auto &t : s->tickets) {
+                Served *v = t.second.get();
+                if (v->admitted && !v->final_) {
+                    v->status = rc;
+                    v->err = g_last_error;
+                    v->final_ = true;
+                    v->t_done = std::chrono::steady_clock::now();
+                    s->runner.finish_query(*v);
+                    s->failed += 1;
+                    s->completed += 1;
+                    s->active -= 1;
+                }
+            }
+            for (Served *v : s->pending) {
+                v->status = rc;
+                v->err = g_last_error;
+                v->final_ = true;
+                s->failed += 1;
+                s->completed += 1;
+            }
+            s->pending.clear();
+            s->cv_done.notify_all();
+            break;
+        }
+    }
+}
+
 }  // namespace
+
+kadabra_server::~kadabra_server()
+{
+    if (worker.joinable()) worker.join();
+    if (io) {
+        (void)hipStreamSynchronize(io);
+        (void)hipStreamDestroy(io);
+    }
+    (void)hipStreamSynchronize(runner.stream);
+    tickets.clear();
+    for (auto &b : bins)
+        for (void *p : b.second) dev_free(p);
+}
 
 extern "C" {
 
@@ -930,6 +1175,8 @@ int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr, co
         HIP_OR_FAIL(alloc_n(u.dst, u.count));
         if (u.count) HIP_OR_FAIL(hipMemcpy(*u.dst, u.src, u.count * sizeof(int32_t), hipMemcpyHostToDevice));
     }
+    // the graph is read by kernels on non-blocking streams: the uploads land first
+    HIP_OR_FAIL(hipDeviceSynchronize());
     *out = g.release();
     return KADABRA_OK;
 }
@@ -1189,5 +1436,217 @@ int kadabra_batch_clear(kadabra_batch *b)
 }
 
 void kadabra_batch_destroy(kadabra_batch *b) { delete b; }
+
+// ---------------------------------------------------------------------------
+// Serving
+// ---------------------------------------------------------------------------
+
+int kadabra_server_create(const kadabra_graph *const *graphs, int32_t ngraphs, int64_t hbm_budget_bytes,
+                          int32_t max_active, kadabra_server **out)
+{
+    g_last_error.clear();
+    if (!out) return fail(KADABRA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!graphs || ngraphs < 1) return fail(KADABRA_EINVAL, "need at least one graph");
+    if (hbm_budget_bytes < 0) return fail(KADABRA_EINVAL, "hbm_budget_bytes must be >= 0");
+    if (max_active < 0 || max_active > 65536) return fail(KADABRA_EINVAL, "max_active must be in [0, 65536]");
+    std::unique_ptr<kadabra_server> s(new (std::nothrow) kadabra_server);
+    if (!s) return fail(KADABRA_ENOMEM, "host allocation failed");
+    for (int32_t i = 0; i < ngraphs; ++i) {
+        if (!graphs[i]) return fail(KADABRA_EINVAL, "graphs[%d] is NULL", i);
+        const GraphData &gd = graphs[i]->gd;
+        s->graphs.push_back(&gd);
+        s->nmax = std::max<int64_t>(s->nmax, gd.n);
+        s->lcap = std::max(s->lcap, gd.vd + 2);
+    }
+    s->max_active = max_active ? max_active : 256;
+    HIP_OR_FAIL(hipGetDevice(&s->device));
+    OK_OR_RETURN(s->runner.init());
+    HIP_OR_FAIL(hipStreamCreateWithFlags(&s->io, hipStreamNonBlocking));
+    int tm;
+    int64_t sl;
+    s->runner.choose_mapping(s->params, s->nmax, s->lcap, &tm, &sl);
+    OK_OR_RETURN(s->runner.ensure_pool(tm, sl, s->nmax, s->lcap, nullptr));
+    s->mapped = true;
+    OK_OR_RETURN(s->runner.ensure_tables(s->max_active, nullptr));
+    if (hbm_budget_bytes == 0) {
+        size_t free_b = 0, total_b = 0;
+        HIP_OR_FAIL(hipMemGetInfo(&free_b, &total_b));
+        hbm_budget_bytes = (int64_t)(free_b / 2);
+    }
+    s->budget = hbm_budget_bytes;
+    kadabra_server *raw = s.get();
+    try {
+        s->worker = std::thread(server_main, raw);
+    } catch (...) {
+        return fail(KADABRA_ENOMEM, "cannot start the worker thread");
+    }
+    *out = s.release();
+    return KADABRA_OK;
+}
+
+int kadabra_server_set_param(kadabra_server *s, const char *key, int64_t value)
+{
+    if (!s || !key) return fail(KADABRA_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->started) return fail(KADABRA_ESTATE, "parameters are fixed once a query was submitted");
+    if (!strcmp(key, "check_interval")) return fail(KADABRA_EINVAL, "check_interval is set per query");
+    if (!strcmp(key, "test_fail_alloc")) return fail(KADABRA_EINVAL, "test_fail_alloc is not supported here");
+    bool known;
+    OK_OR_RETURN(set_common_param(s->params, key, value, &known));
+    if (!known) return fail(KADABRA_EINVAL, "unknown parameter '%s'", key);
+    s->mapped = false;
+    return KADABRA_OK;
+}
+
+int kadabra_server_get_param(const kadabra_server *s, const char *key, int64_t *value)
+{
+    if (!s || !key || !value) return fail(KADABRA_EINVAL, "null argument");
+    if (get_common_param(s->params, key, value) == 0) return KADABRA_OK;
+    if (!strcmp(key, "graphs")) *value = (int64_t)s->graphs.size();
+    else if (!strcmp(key, "max_active")) *value = s->max_active;
+    else if (!strcmp(key, "budget")) *value = s->budget;
+    else return fail(KADABRA_EINVAL, "unknown parameter '%s'", key);
+    return KADABRA_OK;
+}
+
+int kadabra_server_submit(kadabra_server *s, int32_t graph_index, double eps, double delta, uint64_t seed,
+                          int64_t check_interval, int64_t *ticket)
+{
+    if (!s || !ticket) return fail(KADABRA_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->broken != KADABRA_OK)
+        return fail(s->broken, "server stopped after a device error: %s", s->broken_err.c_str());
+    if (s->stop) return fail(KADABRA_ESTATE, "server is shutting down");
+    if (graph_index < 0 || graph_index >= (int32_t)s->graphs.size())
+        return fail(KADABRA_EINVAL, "bad graph index %d", graph_index);
+    std::unique_ptr<Served> v(new (std::nothrow) Served);
+    if (!v) return fail(KADABRA_ENOMEM, "host allocation failed");
+    const GraphData &gd = *s->graphs[(size_t)graph_index];
+    OK_OR_RETURN(make_query(*v, gd, s->params, eps, delta, seed, check_interval));
+    v->charge = s->charge_of(gd);
+    v->frame_bytes = (int64_t)gd.n * 8 * (int64_t)s->params.frames;
+    if (v->charge > s->budget)
+        return fail(KADABRA_ERANGE, "query needs %lld device bytes, budget is %lld", (long long)v->charge,
+                    (long long)s->budget);
+    v->ticket = s->next_ticket++;
+    *ticket = v->ticket;
+    s->pending.push_back(v.get());
+    s->tickets[v->ticket] = std::move(v);
+    s->submitted += 1;
+    s->started = true;
+    s->cv_work.notify_one();
+    return KADABRA_OK;
+}
+
+int kadabra_server_wait(kadabra_server *s, int64_t ticket, double timeout_s, int32_t *done)
+{
+    if (!s) return fail(KADABRA_EINVAL, "null handle");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return fail(KADABRA_EINVAL, "unknown ticket %lld", (long long)ticket);
+    Served *v = it->second.get();
+    if (timeout_s < 0) s->cv_done.wait(lk, [v] { return v->final_; });
+    else s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), [v] { return v->final_; });
+    if (done) *done = v->final_ ? 1 : 0;
+    return KADABRA_OK;
+}
+
+int kadabra_server_result(kadabra_server *s, int64_t ticket, double *scores, int32_t *counts,
+                          kadabra_stats *stats, double *latency_ms)
+{
+    if (!s) return fail(KADABRA_EINVAL, "null handle");
+    Served *v;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->tickets.find(ticket);
+        if (it == s->tickets.end()) return fail(KADABRA_EINVAL, "unknown ticket %lld", (long long)ticket);
+        v = it->second.get();
+        if (!v->final_) return fail(KADABRA_ESTATE, "ticket %lld is not final", (long long)ticket);
+    }
+    if (v->status != KADABRA_OK) return fail(v->status, "%s", v->err.c_str());
+    OK_OR_RETURN(read_result(*v, s->io, scores, counts));
+    if (stats) fill_stats(*v, v->latency_ms, stats);
+    if (latency_ms) *latency_ms = v->latency_ms;
+    return KADABRA_OK;
+}
+
+int kadabra_server_release(kadabra_server *s, int64_t ticket)
+{
+    if (!s) return fail(KADABRA_EINVAL, "null handle");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return fail(KADABRA_EINVAL, "unknown ticket %lld", (long long)ticket);
+    Served *v = it->second.get();
+    if (!v->final_) return fail(KADABRA_ESTATE, "ticket %lld is not final", (long long)ticket);
+    if (v->admitted) {
+        const size_t n = (size_t)v->gd->n;
+        s->put_bin(v->counts, n * sizeof(int32_t));
+        s->put_bin(v->scores, n * sizeof(double));
+        s->put_bin(v->frames, v->frames_len * sizeof(int32_t));
+        v->counts = nullptr;
+        v->scores = nullptr;
+        v->frames = nullptr;
+        v->frames_len = 0;
+        s->in_use -= v->charge;
+        v->charge = 0;
+    }
+    s->tickets.erase(it);
+    s->cv_work.notify_one();
+    return KADABRA_OK;
+}
+
+int kadabra_server_info_get(kadabra_server *s, kadabra_server_info *info, int32_t reset)
+{
+    if (!s || !info) return fail(KADABRA_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    memset(info, 0, sizeof *info);
+    info->submitted = s->submitted;
+    info->completed = s->completed;
+    info->failed = s->failed;
+    info->active = s->active;
+    info->pending = (int64_t)s->pending.size();
+    info->bytes_in_use = s->in_use;
+    info->budget_bytes = s->budget;
+    info->peak_active = s->peak_active;
+    if (!s->lat.empty()) {
+        std::vector<double> l = s->lat;
+        std::sort(l.begin(), l.end());
+        auto rank = [&](double p) {  // nearest-rank percentile
+            size_t r = (size_t)std::ceil(p * (double)l.size());
+            return l[std::min(std::max<size_t>(r, 1), l.size()) - 1];
+        };
+        info->p50_ms = rank(0.50);
+        info->p99_ms = rank(0.99);
+        info->max_ms = l.back();
+    }
+    if (s->queue_n) info->mean_queue_ms = s->queue_ms_sum / (double)s->queue_n;
+    if (reset) {
+        s->lat.clear();
+        s->queue_ms_sum = 0.0;
+        s->queue_n = 0;
+        s->peak_active = s->active;
+    }
+    return KADABRA_OK;
+}
+
+void kadabra_server_destroy(kadabra_server *s)
+{
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->runner.cancel.store(1);
+        for (Served *v : s->pending) {
+            v->status = KADABRA_ECANCELED;
+            v->err = "server destroyed before the query was admitted";
+            v->final_ = true;
+        }
+        s->pending.clear();
+        s->cv_work.notify_all();
+        s->cv_done.notify_all();
+    }
+    delete s;
+}
 
 }  // extern "C"

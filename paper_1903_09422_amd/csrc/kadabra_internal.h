@@ -26,8 +26,10 @@ enum StatIdx {
 // Device control block of one adaptive run (one per query).
 struct Control {
     int32_t viol[2];                 // stopping-rule violations, by epoch parity
-    int32_t err;                     // device-side invariant failure (0 = none)
+    int32_t err;                     // device-side invariant failure (0 = none), by site:
+                                     // 1 level bound, 2 no predecessor, 3 frontier empty
     int32_t pad;
+    int64_t err_sample;              // sample index of the first failure
     int64_t stats[2][ST_COUNT];      // work counters of the epoch in flight, by parity
     int64_t stats_total[ST_COUNT];   // work counters of merged epochs
     int64_t phase_cycles[8];         // per-phase cycles (phase-timer builds only)

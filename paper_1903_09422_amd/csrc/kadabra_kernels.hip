@@ -558,6 +558,7 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
         int64_t dsum0 = row_ptr[s + 1] - row_ptr[s], dsum1 = row_ptr[t + 1] - row_ptr[t];
         u128 fmass0 = 1, fmass1 = 1;  // sum of the frontier's sigma
         int X = 0, nN = 0, nM = 0;
+        int fail_site = 0;
         bool ok = true, retry = false;
         T::sync();
         for (;;) {
@@ -570,6 +571,7 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
             const int64_t dsx = X ? dsum1 : dsum0;
             if (lvlx + 3 > a.st.lcap) {  // more levels than the diameter bound allows
                 ok = false;
+                fail_site = 1;
                 nN = 0;
                 break;
             }
@@ -674,11 +676,13 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
             nM = uniform_i32(sm.nmeet);
             if (probe && nM == 0) {  // no meeting on this level: expand it in full
                 retry = true;
+                T::sync();  // every wave has read the counters before they are reset
                 continue;
             }
             retry = false;
             if (nN == 0) {  // cannot happen inside one component
                 ok = false;
+                fail_site = 3;
                 break;
             }
             // rescale the new level if its largest count may reach 2^SIGMA_BITS
@@ -794,7 +798,9 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                     __syncthreads();
                     pick_by_id_prefix<TEAM>(sm.sv, sm.sw, nM, (u128)r, &sm.pick);
                     __syncthreads();
-                    v = sm.pick;
+                    v = uniform_i32(sm.pick);
+                    // every wave holds v before backtracking resets sm.pick
+                    __syncthreads();
                 } else {
                     // smallest id v whose inclusive prefix (ascending ids) exceeds r
                     int32_t lo = nv - (int32_t)mn, hi = (int32_t)mx - 1;
@@ -906,7 +912,8 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                     x = uniform_i32(sm.pick);
                     __syncthreads();
                     if (x < 0) {  // no predecessor found: cannot happen on a BFS level
-                        if (lane == 0) atomicExch(&qctl->err, 2);
+                        if (lane == 0 && atomicCAS(&qctl->err, 0, 2) == 0)
+                            atomicExch((unsigned long long *)&qctl->err_sample, (unsigned long long)i);
                         ok = false;
                         break;
                     }
@@ -917,8 +924,8 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                     }
                 }
             }
-        } else if (lane == 0) {
-            atomicExch(&qctl->err, 1);
+        } else if (lane == 0 && atomicCAS(&qctl->err, 0, fail_site) == 0) {
+            atomicExch((unsigned long long *)&qctl->err_sample, (unsigned long long)i);
         }
         PHASE_MARK(4);
 

@@ -290,6 +290,31 @@ def batch_pool(seed: int = 1):
     return out
 
 
+def serve_pool(seed: int = 1, with_rmat22: bool = True):
+    """Graphs of the served workload: the 64 graphs of batch_pool, the
+    perturbed 1024 x 1024 grid and (optionally) R-MAT scale 22, edge factor 16."""
+    pool = [g for g, *_ in batch_pool(seed)]
+    pool.append(perturbed_grid(1024, seed=1))
+    if with_rmat22:
+        pool.append(rmat(22, 16, seed=1))
+    return pool
+
+
+def serve_trace(num_graphs: int, num_queries: int = 256, seed: int = 7):
+    """A seeded query stream for serving: each query picks a graph uniformly,
+    eps from {0.05, 0.01}, delta 0.1, checks every 16384 samples, and its own
+    sampling seed; unit-rate exponential gaps (scaled to a rate by the caller)
+    give Poisson arrivals.  Returns (queries, gaps): queries as
+    (graph_index, eps, delta, check_interval, query_seed)."""
+    rng = np.random.default_rng(seed)
+    gi = rng.integers(0, num_graphs, num_queries)
+    eps = np.array([0.05, 0.01])[rng.integers(0, 2, num_queries)]
+    queries = [(int(gi[i]), float(eps[i]), 0.1, 16384, 5000 + i) for i in range(num_queries)]
+    gaps = rng.exponential(1.0, num_queries)
+    gaps[0] = 0.0
+    return queries, gaps
+
+
 # --------------------------------------------------------------------------
 # Small named graphs (closed forms and brute force)
 # --------------------------------------------------------------------------

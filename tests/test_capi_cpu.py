@@ -89,6 +89,15 @@ def test_null_arguments():
     rc = L.kadabra_create_graph(4, 0, None, None, None)
     assert rc == _lib.EINVAL
     assert L.kadabra_eval_stop_fg(0, None, 1, 1, 1.0, None, None) == _lib.EINVAL
+    out = C.c_void_p(99)
+    assert L.kadabra_server_create(None, 0, 0, 0, C.byref(out)) == _lib.EINVAL
+    assert out.value is None
+    assert L.kadabra_server_submit(None, 0, 0.1, 0.1, 1, 8, None) == _lib.EINVAL
+    assert L.kadabra_server_wait(None, 1, 0.0, None) == _lib.EINVAL
+    assert L.kadabra_server_result(None, 1, None, None, None, None) == _lib.EINVAL
+    assert L.kadabra_server_release(None, 1) == _lib.EINVAL
+    assert L.kadabra_server_info_get(None, None, 0) == _lib.EINVAL
+    L.kadabra_server_destroy(None)  # no-op
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):

@@ -1,0 +1,169 @@
+"""Serving with continuous batching: queries submitted at any time join the
+running launches at the next round boundary; each result equals the oracle's
+and the query's own single run, bit for bit, whatever else was in flight.
+Admission respects the device-memory budget."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_09422_amd import Graph, KadabraError, Server, _lib
+from paper_1903_09422_amd import graphs as G
+
+pytestmark = pytest.mark.gpu
+
+WORK_KEYS = ("v_exp", "e_scan", "e_bt", "path_interior", "disconnected")
+
+MIX = [
+    (G.erdos_renyi(600, 6.0, seed=11), 0.05, 128),
+    (G.rmat(10, 16, seed=5), 0.04, 256),
+    (G.rhg(1 << 11, 10.0, 2.8, seed=7), 0.05, 200),
+    (G.grid_graph(20, 20), 0.05, 64),
+    (G.star_graph(30), 0.1, 33),
+    (G.disjoint_union(G.grid_graph(6, 6), G.cycle_graph(9)), 0.05, 77),
+]
+
+
+def _same(got, want):
+    assert got.tau == want.tau
+    assert np.array_equal(got.counts, want.counts)
+    for k in WORK_KEYS:
+        assert got.stats[k] == want.stats[k], k
+
+
+def _charge(n, frames=1):
+    return n * (4 + 8 + 8 * frames)
+
+
+def test_serve_staggered_equals_oracle():
+    """Queries arrive while others run (two submitting threads, random gaps);
+    every result equals the oracle's."""
+    print("case serve staggered mix", flush=True)
+    handles = [Graph.from_csr(g) for g, *_ in MIX]
+    jobs = [(k, seed) for seed in (3, 4) for k in range(len(MIX))]
+    tickets = {}
+    lock = threading.Lock()
+    with Server(handles) as srv:
+        def submitter(part, rng_seed):
+            rng = np.random.default_rng(rng_seed)
+            for k, seed in part:
+                time.sleep(float(rng.uniform(0, 0.004)))
+                g, eps, n_check = MIX[k]
+                t = srv.submit(k, eps, 0.1, seed, n_check)
+                with lock:
+                    tickets[(k, seed)] = t
+
+        th = [threading.Thread(target=submitter, args=(jobs[i::2], i)) for i in range(2)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        for (k, seed), t in sorted(tickets.items()):
+            assert srv.wait(t, timeout=60.0)
+            g, eps, n_check = MIX[k]
+            got, lat = srv.result(t, k)
+            _same(got, oracle.run(g, eps, 0.1, seed, n_check))
+            np.testing.assert_array_equal(got.scores, got.counts / float(got.tau))
+            assert lat > 0 and got.stats["ms_total"] == lat
+            srv.release(t)
+        info = srv.info()
+        assert info["completed"] == len(jobs) and info["failed"] == 0
+        assert info["active"] == 0 and info["pending"] == 0 and info["bytes_in_use"] == 0
+        assert info["p50_ms"] <= info["p99_ms"] <= info["max_ms"]
+    for h in handles:
+        h.close()
+
+
+def test_serve_budget_gates_admission():
+    """With a budget of one query's memory, a second query waits (not final,
+    its result and release refused) until the first is released; then it runs
+    and equals its own single run."""
+    g, eps, n_check = MIX[1]
+    print("case serve budget gate", flush=True)
+    with Graph.from_csr(g) as h:
+        with Server([h], hbm_budget_bytes=_charge(g.n)) as srv:
+            a = srv.submit(0, eps, 0.1, 21, n_check)
+            b = srv.submit(0, eps, 0.1, 22, n_check)
+            assert srv.wait(a, timeout=60.0)
+            # a's counters and score buffer stay charged until release: b waits
+            assert not srv.wait(b, timeout=0.2)
+            inf = srv.info()
+            assert inf["pending"] == 1 and inf["active"] == 0
+            assert inf["bytes_in_use"] == g.n * 12 <= inf["budget_bytes"]
+            for call in (lambda: srv.result(b, 0), lambda: srv.release(b)):
+                with pytest.raises(KadabraError) as e:
+                    call()
+                assert e.value.status == _lib.ESTATE
+            got_a, _ = srv.result(a, 0)
+            srv.release(a)
+            assert srv.wait(b, timeout=60.0)
+            got_b, _ = srv.result(b, 0)
+            srv.release(b)
+            assert srv.info()["peak_active"] == 1
+        for seed, got in ((21, got_a), (22, got_b)):
+            h.set_param("check_interval", n_check)
+            h.run(eps, 0.1, seed)
+            _same(got, h.result())
+
+
+def test_serve_many_in_flight_and_buffer_reuse():
+    """A burst of 24 queries over three graphs runs in shared launches
+    (peak > 1), reusing released buffers; every result equals its single run."""
+    graphs = [MIX[0][0], MIX[2][0], MIX[3][0]]
+    handles = [Graph.from_csr(g) for g in graphs]
+    print("case serve burst", flush=True)
+    want = {}
+    for k, h in enumerate(handles):
+        h.set_param("check_interval", 96)
+        for seed in range(8):
+            h.run(0.05, 0.1, 100 + seed)
+            want[(k, seed)] = h.result()
+    with Server(handles, max_active=16) as srv:
+        for rnd in range(2):  # a second round reuses the binned buffers
+            tk = {(k, s): srv.submit(k, 0.05, 0.1, 100 + s, 96) for k in range(3) for s in range(8)}
+            for (k, s), t in tk.items():
+                assert srv.wait(t, timeout=60.0)
+                got, _ = srv.result(t, k, scores=(rnd == 0))
+                _same(got, want[(k, s)])
+                srv.release(t)
+        inf = srv.info()
+        assert 1 < inf["peak_active"] <= 16
+        assert inf["completed"] == 48 and inf["bytes_in_use"] == 0
+    for h in handles:
+        h.close()
+
+
+def test_serve_errors_and_shutdown():
+    g, eps, n_check = MIX[3]
+    print("case serve errors", flush=True)
+    with Graph.from_csr(g) as h:
+        srv = Server([h], hbm_budget_bytes=_charge(g.n))
+        for call, status in ((lambda: srv.submit(1, eps, 0.1, 1, n_check), _lib.EINVAL),
+                             (lambda: srv.submit(0, 1.5, 0.1, 1, n_check), _lib.EINVAL),
+                             (lambda: srv.wait(12345, 0.0), _lib.EINVAL),
+                             (lambda: srv.result(12345, 0), _lib.EINVAL),
+                             (lambda: srv.release(12345), _lib.EINVAL)):
+            with pytest.raises(KadabraError) as e:
+                call()
+            assert e.value.status == status
+        srv.set_param("frames", 2)  # before the first submit: allowed, doubles the frames
+        with pytest.raises(KadabraError) as e:
+            srv.submit(0, eps, 0.1, 1, n_check)  # now needs more than the budget
+        assert e.value.status == _lib.ERANGE
+        srv.close()
+        srv = Server([h])
+        assert srv.get_param("graphs") == 1 and srv.get_param("max_active") == 256
+        t = srv.submit(0, eps, 0.1, 5, n_check)
+        with pytest.raises(KadabraError) as e:
+            srv.set_param("team", 64)
+        assert e.value.status == _lib.ESTATE
+        srv.wait(t, timeout=60.0)
+        # destroy with work queued: pending queries are canceled, running ones
+        # stop at their next boundary, and the call returns
+        for s in range(20):
+            srv.submit(0, 0.01, 0.1, 1000 + s, 8)
+        t0 = time.time()
+        srv.close()
+        assert time.time() - t0 < 30.0
