@@ -412,8 +412,12 @@ struct SampleShared {
     int32_t nnext, nmeet, pick, ncand;
 };
 
+// A const int32 in the global address space, and the cast to it.
+typedef const __attribute__((address_space(1))) int32_t gint32_t;
+__device__ __forceinline__ gint32_t *as_global(const int32_t *p) { return (gint32_t *)p; }
+
 // lower bound of `key` in the sorted row col[0, len): true if present
-__device__ __forceinline__ bool row_contains(const int32_t *row, int32_t len, int32_t key)
+__device__ __forceinline__ bool row_contains(gint32_t *row, int32_t len, int32_t key)
 {
     int32_t lo = 0, hi = len;
     while (lo < hi) {
@@ -445,6 +449,7 @@ template <int TEAM>
 __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
 {
     using T = Team<TEAM>;
+    constexpr int ARCS = (TEAM == 64) ? 4 : 8;  // arcs in flight per lane in a level expansion
     constexpr int STAGE = Cap<TEAM>::STAGE;
     __shared__ SampleShared<TEAM> sm;
     const int lane = threadIdx.x;
@@ -510,9 +515,11 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
         // stream order has already run that check, so its flag decides
         if (qgate >= 0 && qctl->viol[qgate] == 0) continue;
         const int64_t i = qd->lo + (jc - qd->claim_begin);
-        const int32_t *const row_ptr = qd->row_ptr;
-        const int32_t *const col = qd->col;
-        const int32_t *const comp = qd->comp;
+        // graph arrays live in device global memory: say so, so that their
+        // loads are global (not flat) instructions
+        const gint32_t *const row_ptr = as_global(qd->row_ptr);
+        const gint32_t *const col = as_global(qd->col);
+        const gint32_t *const comp = as_global(qd->comp);
         const int32_t nv = qd->n;
         const uint64_t seed = qd->seed;
         const int64_t probe_min = qd->probe_min, num_arcs = qd->num_arcs;
@@ -617,10 +624,10 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                 sm.cpfx[lane] = ex;
                 const int32_t cnt = min(TEAM, fhix - c0);
                 __syncthreads();
-                // Each lane takes arcs lane, lane + TEAM, ... two at a time: both
-                // owners, column entries and code words are fetched before
-                // either is processed.  A lane's owners only move forward, so
-                // each is found by galloping from the previous one.
+                // Each lane takes arcs lane, lane + TEAM, ... ARCS at a time: all
+                // their owners, column entries and code words are fetched before
+                // any is processed.  A lane's owners only move forward, so each
+                // is found by galloping from the previous one.
                 int32_t own = 0;
                 auto owner_of = [&](int32_t e) {
                     int32_t step = 1;
@@ -635,39 +642,74 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                     }
                     return own;
                 };
-                auto visit = [&](int32_t w, uint32_t word, int32_t o) {
-                    uint32_t *const cw = &code[w >> 3];
-                    const int shx = code_shift(w, X), shy = code_shift(w, X ^ 1);
-                    uint32_t dx = (word >> shx) & 3u;
-                    const uint32_t dy = (word >> shy) & 3u;
-                    bool claimed = false;
-                    if (dx == 0u && (!probe || dy != 0u)) {
-                        // every claim on this level writes the same code, so an
-                        // OR into a field another lane just set changes nothing
-                        const uint32_t old = (wg_or_u32(cw, code_new << shx) >> shx) & 3u;
-                        claimed = (old == 0u);
-                        dx = claimed ? code_new : old;
+                for (int32_t e = lane; e < tot; e += ARCS * TEAM) {
+                    // owners and arc positions (LDS only); an arc past the end
+                    // repeats arc e so that every load below is unconditional
+                    int32_t ow[ARCS], ai[ARCS], wv[ARCS];
+                    uint32_t wd[ARCS];
+#pragma unroll
+                    for (int k = 0; k < ARCS; ++k) {
+                        const int32_t ek = e + k * TEAM;
+                        if (k == 0 || ek < tot) {
+                            ow[k] = owner_of(ek);
+                            ai[k] = sm.crs[ow[k]] + (ek - sm.cpfx[ow[k]]);
+                        } else {
+                            ow[k] = ow[0];
+                            ai[k] = ai[0];
+                        }
                     }
-                    const int p = wave_append(claimed, &sm.nnext);
-                    if (claimed) ballx[base_new + p] = w;
-                    const bool is_meet = claimed && dy != 0u;
-                    const int q = wave_append(is_meet, &sm.nmeet);
-                    if (is_meet) meet[q] = w;
-                    if (dx == code_new) atomic_add_sigma(&sigx[w], to128(sm.cm[o]));
-                };
-                for (int32_t e = lane; e < tot; e += 2 * TEAM) {
-                    const int32_t e2 = e + TEAM;
-                    const int32_t o1 = owner_of(e);
-                    const int32_t w1 = col[sm.crs[o1] + (e - sm.cpfx[o1])];
-                    int32_t o2 = o1, w2 = -1;
-                    if (e2 < tot) {
-                        o2 = owner_of(e2);
-                        w2 = col[sm.crs[o2] + (e2 - sm.cpfx[o2])];
+#pragma unroll
+                    for (int k = 0; k < ARCS; ++k) wv[k] = col[ai[k]];
+#pragma unroll
+                    for (int k = 0; k < ARCS; ++k) wd[k] = code[wv[k] >> 3];
+                    // claims: decided from the words read, and all issued before
+                    // any result is awaited.  Every claim on this level writes the
+                    // same code, so an OR into a field another lane (or an earlier
+                    // arc of this lane) just set changes nothing.
+                    uint32_t dxc[ARCS], dyc[ARCS], old[ARCS];
+                    bool cand[ARCS];
+#pragma unroll
+                    for (int k = 0; k < ARCS; ++k) {
+                        const bool valid = k == 0 || e + k * TEAM < tot;
+                        dxc[k] = (wd[k] >> code_shift(wv[k], X)) & 3u;
+                        dyc[k] = (wd[k] >> code_shift(wv[k], X ^ 1)) & 3u;
+                        cand[k] = valid && dxc[k] == 0u && (!probe || dyc[k] != 0u);
                     }
-                    const uint32_t word1 = code[w1 >> 3];
-                    const uint32_t word2 = (w2 >= 0) ? code[w2 >> 3] : 0u;
-                    visit(w1, word1, o1);
-                    if (w2 >= 0) visit(w2, word2, o2);
+#pragma unroll
+                    for (int k = 0; k < ARCS; ++k)
+                        old[k] = cand[k] ? wg_or_u32(&code[wv[k] >> 3], code_new << code_shift(wv[k], X)) : 0u;
+                    bool add[ARCS];
+#pragma unroll
+                    for (int k = 0; k < ARCS; ++k) {
+                        const int32_t w = wv[k];
+                        bool claimed = false;
+                        if (cand[k]) {
+                            const uint32_t o = (old[k] >> code_shift(w, X)) & 3u;
+                            claimed = (o == 0u);
+                            dxc[k] = claimed ? code_new : o;
+                        }
+                        const int p = wave_append(claimed, &sm.nnext);
+                        if (claimed) ballx[base_new + p] = w;
+                        const bool is_meet = claimed && dyc[k] != 0u;
+                        const int q = wave_append(is_meet, &sm.nmeet);
+                        if (is_meet) meet[q] = w;
+                        add[k] = (k == 0 || e + k * TEAM < tot) && dxc[k] == code_new;
+                    }
+                    // sigma(w) += sigma(owner) for every arc into the new level:
+                    // all low-word adds first, then the carries into the high words
+                    uint64_t olo[ARCS];
+#pragma unroll
+                    for (int k = 0; k < ARCS; ++k) olo[k] = 0u;
+#pragma unroll
+                    for (int k = 0; k < ARCS; ++k)
+                        if (add[k]) olo[k] = wg_add_u64(&sigx[wv[k]].lo, sm.cm[ow[k]].lo);
+#pragma unroll
+                    for (int k = 0; k < ARCS; ++k) {
+                        if (!add[k]) continue;
+                        const Sigma m = sm.cm[ow[k]];
+                        const uint64_t hi = m.hi + ((olo[k] + m.lo) < olo[k] ? 1u : 0u);
+                        if (hi) wg_add_u64(&sigx[wv[k]].hi, hi);
+                    }
                 }
                 __syncthreads();
             }
