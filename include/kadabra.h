@@ -86,8 +86,8 @@ int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr,
  *   "check_interval"  N >= 1: the stopping rule is checked after every N
  *                     samples (Appendix C.2).  Default 1024.  The only key
  *                     that changes results.
- *   "team"            0 (auto), 64 (one wavefront per sample) or 256 (one
- *                     workgroup per sample).  Default 0.
+ *   "team"            0 (auto), 64 (one wavefront per sample), 128 (two)
+ *                     or 256 (four wavefronts per sample).  Default 0.
  *   "slots"           samples in flight, 0 = auto (bounded by device memory).
  *   "frames"          counter frames F >= 1 the workgroups' increments are
  *                     spread over, merged at every boundary.  Default 1.

@@ -236,7 +236,8 @@ int set_common_param(Params &p, const char *key, int64_t value, bool *known)
         if (value < 1 || value > INT32_MAX) return fail(KADABRA_EINVAL, "check_interval must be in [1, 2^31)");
         p.check_interval = value;
     } else if (!strcmp(key, "team")) {
-        if (value != 0 && value != 64 && value != 256) return fail(KADABRA_EINVAL, "team must be 0, 64 or 256");
+        if (value != 0 && value != 64 && value != 128 && value != 256 && value != 512)
+            return fail(KADABRA_EINVAL, "team must be 0, 64, 128, 256 or 512");
         p.team = (int)value;
     } else if (!strcmp(key, "slots")) {
         if (value < 0 || value > (1 << 20)) return fail(KADABRA_EINVAL, "slots must be in [0, 2^20]");
@@ -497,7 +498,7 @@ struct Runner {
         int t = p.team ? p.team : 256;
         int64_t s = p.slots;
         if (s == 0) {
-            s = (int64_t)std::max(num_cu, 1) * ((t == 64) ? 8 : 4);
+            s = (int64_t)std::max(num_cu, 1) * ((t == 512) ? 2 : (t == 256) ? 4 : 8);
             size_t free_b = 0, total_b = 0;
             if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0) {
                 free_b += pool_bytes();

@@ -394,7 +394,7 @@ __device__ __forceinline__ int wave_append(bool take, int32_t *cnt)
 // LDS staging capacity for the meeting set and for backtracking candidates
 template <int TEAM>
 struct Cap {
-    static constexpr int STAGE = (TEAM == 64) ? 256 : 1024;
+    static constexpr int STAGE = (TEAM == 64) ? 256 : (TEAM == 128) ? 512 : 1024;
 };
 
 template <int TEAM>
@@ -405,7 +405,7 @@ struct SampleShared {
     Sigma cm[TEAM];                   // frontier chunk: sigma of the vertex
     int32_t sv[Cap<TEAM>::STAGE];     // staged meeting vertices / candidates
     Sigma sw[Cap<TEAM>::STAGE];       // their weights
-    uint64_t red[16];                 // team reduction scratch
+    uint64_t red[4 * (TEAM / 64) < 16 ? 16 : 4 * (TEAM / 64)];  // team reduction scratch (4 words a wave)
     uint64_t acc[ST_COUNT];           // work counters of the query being served (lane 0)
     int64_t claim;                    // claimed launch-wide sample index
     int32_t query;                    // its query
@@ -446,7 +446,7 @@ __device__ __forceinline__ void pick_by_id_prefix(const int32_t *sv, const Sigma
 // Wave/workgroup-per-sample sampler.  Every lane of the team runs the same
 // control flow; per-sample scalars live in registers (uniform) or LDS.
 template <int TEAM>
-__global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
+__global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void sample_kernel(SampleArgs a)
 {
     using T = Team<TEAM>;
     constexpr int ARCS = (TEAM == 64) ? 4 : 8;  // arcs in flight per lane in a level expansion
@@ -890,11 +890,15 @@ __global__ __launch_bounds__(TEAM) void sample_kernel(SampleArgs a)
                     __syncthreads();
                     bool done = false;
                     if ((int64_t)(lhi - llo) * 24 < (int64_t)deg) {
-                        // short level, long row: probe each level vertex in x's
-                        // sorted row; stage the candidates with their counts
+                        // short level, long row: test each level vertex p for
+                        // adjacency to x by a binary search in the shorter of the
+                        // two sorted rows (the graph is symmetric); stage the
+                        // candidates with their counts
                         for (int32_t k = llo + lane; k < lhi; k += TEAM) {
                             const int32_t p = balls[k];
-                            const bool hit = row_contains(col + rs, deg, p);
+                            const int32_t prs = row_ptr[p], pdeg = row_ptr[p + 1] - prs;
+                            const bool hit = (pdeg < deg) ? row_contains(col + prs, pdeg, x)
+                                                          : row_contains(col + rs, deg, p);
                             const int at = wave_append(hit, &sm.ncand);
                             if (hit && at < STAGE) {
                                 sm.sv[at] = p;
@@ -1095,8 +1099,12 @@ hipError_t launch_sample(int team, int slots, const SampleArgs &a, hipStream_t s
 {
     if (team == 64)
         hipLaunchKernelGGL(sample_kernel<64>, dim3(slots), dim3(64), 0, s, a);
+    else if (team == 128)
+        hipLaunchKernelGGL(sample_kernel<128>, dim3(slots), dim3(128), 0, s, a);
     else if (team == 256)
         hipLaunchKernelGGL(sample_kernel<256>, dim3(slots), dim3(256), 0, s, a);
+    else if (team == 512)
+        hipLaunchKernelGGL(sample_kernel<512>, dim3(slots), dim3(512), 0, s, a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -36,7 +36,7 @@ def _same(got, want):
         assert got.stats[k] == want.stats[k], k
 
 
-@pytest.mark.parametrize("team,overlap", [(256, 1), (64, 1), (256, 0)])
+@pytest.mark.parametrize("team,overlap", [(256, 1), (128, 1), (64, 1), (256, 0)])
 def test_batch_mix_equals_oracle(team, overlap):
     print(f"case batch mix team={team} overlap={overlap}", flush=True)
     handles = [Graph.from_csr(g) for g, *_ in MIX]
@@ -105,7 +105,7 @@ def test_autotune_is_result_neutral():
     with Graph.from_csr(g) as dev:
         dev.set_param("check_interval", n_check)
         chosen = dev.autotune(eps, delta, trial_samples=4096)
-        assert chosen["team"] in (64, 256) and chosen["slots"] > 0
+        assert chosen["team"] in (64, 128, 256) and chosen["slots"] > 0
         dev.run(eps, delta, ref["seed"])
         got = dev.result()
     assert got.tau == ref["tau"]

@@ -54,7 +54,7 @@ SMALL = [
 ]
 
 
-@pytest.mark.parametrize("team,probe", [(64, -1), (256, -1), (64, 0), (256, 0)])
+@pytest.mark.parametrize("team,probe", [(64, -1), (128, -1), (256, -1), (512, -1), (64, 0), (128, 0), (256, 0)])
 @pytest.mark.parametrize("g", SMALL, ids=lambda g: g.name)
 def test_small_graphs(g, team, probe):
     print(f"case {g.name} team={team} probe_min={probe}", flush=True)
@@ -94,7 +94,7 @@ def test_er4096_workload():
     g, eps, delta, n_check = G.workload("er4096")
     print("case er4096 full", flush=True)
     want = oracle.run(g, eps, delta, 1, n_check)
-    for team in (64, 256):
+    for team in (64, 128, 256, 512):
         assert_same(gpu_run(g, eps, delta, 1, n_check, team=team), want)
 
 
@@ -134,7 +134,8 @@ def test_mapping_does_not_change_results():
     g, eps, delta, n_check = G.workload("rmat18")
     print("case rmat18 mappings", flush=True)
     base = gpu_run(g, eps, delta, 5, n_check, team=256)
-    for params in ({"team": 64}, {"team": 256, "slots": 37}, {"team": 64, "slots": 1000},
+    for params in ({"team": 64}, {"team": 128}, {"team": 512}, {"team": 256, "slots": 37}, {"team": 64, "slots": 1000},
+                   {"team": 128, "slots": 2048},
                    {"frames": 8}, {"overlap": 0}, {"team": 64, "frames": 3, "overlap": 0},
                    {"probe_min": 0}, {"probe_min": 1 << 40}, {"team": 64, "probe_min": 0}):
         print("  mapping", params, flush=True)
@@ -189,7 +190,7 @@ def test_errors_and_state():
             dev.set_param("nonsense", 1)
         assert e.value.status == _lib.EINVAL
         with pytest.raises(KadabraError):
-            dev.set_param("team", 128)
+            dev.set_param("team", 96)
         # forced allocation failure: ENOMEM, no result, handle still usable
         dev.set_param("test_fail_alloc", 3)
         with pytest.raises(KadabraError) as e:
