@@ -292,8 +292,10 @@ int kadabra_server_info_get(kadabra_server *s, kadabra_server_info *info, int32_
  * everything (NULL is a no-op). */
 void kadabra_server_destroy(kadabra_server *s);
 
-/* Asks a run in progress on another thread to stop at its next boundary
- * (kadabra_run then returns ECANCELED).  Safe to call concurrently. */
+/* Asks a run in progress on another thread (its setup included) to stop at
+ * its next boundary (kadabra_run then returns ECANCELED).  Each kadabra_run or
+ * kadabra_autotune clears earlier requests when it starts.  Safe to call
+ * concurrently. */
 int kadabra_cancel(kadabra_graph *g);
 
 /* Frees the handle and its device memory (NULL is a no-op). */

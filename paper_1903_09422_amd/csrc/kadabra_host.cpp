@@ -567,7 +567,6 @@ int Runner::run(std::vector<Query *> &queries, const Params &p,
                 const std::function<void(std::vector<Query *> &)> &admit, int64_t sample_cap,
                 int64_t *fail_countdown, const std::function<void(Query *)> &on_done)
 {
-    cancel.store(0);
     std::vector<Query *> active;
     auto take_new = [&](std::vector<Query *> &incoming) -> int {
         for (Query *q : incoming) {
@@ -1215,6 +1214,7 @@ int kadabra_set_stream(kadabra_graph *g, void *hip_stream)
 int kadabra_run(kadabra_graph *g, double eps, double delta, uint64_t seed)
 {
     if (!g) return fail(KADABRA_EINVAL, "null handle");
+    g->runner.cancel.store(0);  // a cancel from now on, setup included, stops this run
     g_last_error.clear();
     const auto t0 = std::chrono::steady_clock::now();
     g->have_result = false;
@@ -1231,6 +1231,7 @@ int kadabra_autotune(kadabra_graph *g, double eps, double delta, int64_t trial_s
 {
     if (!g) return fail(KADABRA_EINVAL, "null handle");
     if (trial_samples < 1) return fail(KADABRA_EINVAL, "trial_samples must be >= 1");
+    g->runner.cancel.store(0);
     g_last_error.clear();
     g->have_result = false;
     OK_OR_RETURN(ensure_graph_query(g, eps, delta, 0x5EEDull));
@@ -1387,6 +1388,7 @@ int kadabra_batch_run(kadabra_batch *b)
 {
     if (!b) return fail(KADABRA_EINVAL, "null handle");
     if (b->queries.empty()) return fail(KADABRA_ESTATE, "empty batch");
+    b->runner.cancel.store(0);
     g_last_error.clear();
     const auto t0 = std::chrono::steady_clock::now();
     b->have_result = false;
@@ -1409,6 +1411,7 @@ int kadabra_batch_autotune(kadabra_batch *b, int64_t trial_samples)
     if (!b) return fail(KADABRA_EINVAL, "null handle");
     if (b->queries.empty()) return fail(KADABRA_ESTATE, "empty batch");
     if (trial_samples < 1) return fail(KADABRA_EINVAL, "trial_samples must be >= 1");
+    b->runner.cancel.store(0);
     b->have_result = false;
     std::vector<Query *> qs;
     for (auto &q : b->queries) qs.push_back(q.get());

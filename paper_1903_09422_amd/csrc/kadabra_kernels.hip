@@ -399,12 +399,16 @@ struct Cap {
 
 template <int TEAM>
 struct SampleShared {
-    int32_t cu[TEAM];                 // frontier chunk: vertex
     int32_t crs[TEAM];                // frontier chunk: first arc
     int32_t cpfx[TEAM];               // frontier chunk: exclusive prefix of degrees
     Sigma cm[TEAM];                   // frontier chunk: sigma of the vertex
-    int32_t sv[Cap<TEAM>::STAGE];     // staged meeting vertices / candidates
+    int32_t sv[Cap<TEAM>::STAGE];     // staged new level / meeting vertices / candidates
     Sigma sw[Cap<TEAM>::STAGE];       // their weights
+    // per side, the frontier when it fits one chunk (filled when the level is
+    // completed, read when that side expands next): first arc, degree, sigma
+    int32_t frs[2][TEAM];
+    int32_t fdg[2][TEAM];
+    Sigma fsg[2][TEAM];
     uint64_t red[4 * (TEAM / 64) < 16 ? 16 : 4 * (TEAM / 64)];  // team reduction scratch (4 words a wave)
     uint64_t acc[ST_COUNT];           // work counters of the query being served (lane 0)
     int64_t claim;                    // claimed launch-wide sample index
@@ -449,7 +453,7 @@ template <int TEAM>
 __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void sample_kernel(SampleArgs a)
 {
     using T = Team<TEAM>;
-    constexpr int ARCS = (TEAM == 64) ? 4 : 8;  // arcs in flight per lane in a level expansion
+    constexpr int ARCS = (TEAM == 64) ? 4 : 8;     // arcs in flight per lane in a level expansion
     constexpr int STAGE = Cap<TEAM>::STAGE;
     __shared__ SampleShared<TEAM> sm;
     const int lane = threadIdx.x;
@@ -562,7 +566,17 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
         // per-side BFS state (uniform across the team; side X selected by value)
         int32_t lvl0 = 0, lvl1 = 0;
         int32_t flo0 = 0, flo1 = 0, fhi0 = 1, fhi1 = 1;  // frontier = ball[flo, fhi)
-        int64_t dsum0 = row_ptr[s + 1] - row_ptr[s], dsum1 = row_ptr[t + 1] - row_ptr[t];
+        const int32_t rs_s = row_ptr[s], rs_t = row_ptr[t];
+        int64_t dsum0 = row_ptr[s + 1] - rs_s, dsum1 = row_ptr[t + 1] - rs_t;
+        bool fc0 = true, fc1 = true;  // the side's frontier is in the LDS cache
+        if (lane == 0) {
+            sm.frs[0][0] = rs_s;
+            sm.fdg[0][0] = (int32_t)dsum0;
+            sm.fsg[0][0] = Sigma{1u, 0u};
+            sm.frs[1][0] = rs_t;
+            sm.fdg[1][0] = (int32_t)dsum1;
+            sm.fsg[1][0] = Sigma{1u, 0u};
+        }
         u128 fmass0 = 1, fmass1 = 1;  // sum of the frontier's sigma
         int X = 0, nN = 0, nM = 0;
         int fail_site = 0;
@@ -607,17 +621,22 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
             const uint32_t code_new = level_code(lvlx + 1);  // code of the new level
             const int32_t base_new = fhix;
             __syncthreads();
+            const bool fcx = X ? fc1 : fc0;  // then the frontier is one chunk
             for (int32_t c0 = flox; c0 < fhix; c0 += TEAM) {
                 const int32_t idx = c0 + lane;
                 int32_t dg = 0;
                 if (idx < fhix) {
-                    const int32_t u = ballx[idx];
-                    const int32_t rs = row_ptr[u];
-                    dg = row_ptr[u + 1] - rs;
-                    const Sigma m = sigx[u];
-                    sm.cu[lane] = u;
-                    sm.crs[lane] = rs;
-                    sm.cm[lane] = m;
+                    if (fcx) {
+                        dg = sm.fdg[X][lane];
+                        sm.crs[lane] = sm.frs[X][lane];
+                        sm.cm[lane] = sm.fsg[X][lane];
+                    } else {
+                        const int32_t u = ballx[idx];
+                        const int32_t rs = row_ptr[u];
+                        dg = row_ptr[u + 1] - rs;
+                        sm.crs[lane] = rs;
+                        sm.cm[lane] = sigx[u];
+                    }
                 }
                 int32_t tot;
                 const int32_t ex = T::excl_scan_i32(dg, &tot, sm.red);
@@ -689,7 +708,10 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                             dxc[k] = claimed ? code_new : o;
                         }
                         const int p = wave_append(claimed, &sm.nnext);
-                        if (claimed) ballx[base_new + p] = w;
+                        if (claimed) {
+                            ballx[base_new + p] = w;
+                            if (p < STAGE) sm.sv[p] = w;
+                        }
                         const bool is_meet = claimed && dyc[k] != 0u;
                         const int q = wave_append(is_meet, &sm.nmeet);
                         if (is_meet) meet[q] = w;
@@ -749,15 +771,25 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
             }
             PHASE_MARK(2);
             if (nM > 0) break;
-            // advance side X: its frontier becomes the new level
+            // advance side X: its frontier becomes the new level (ids staged in
+            // LDS by the claims when they fit; a one-chunk level is cached)
             uint64_t ds = 0;
             u128 ms = 0;
+            const bool staged_new = nN <= STAGE, cache_new = nN <= TEAM;
             for (int32_t k = lane; k < nN; k += TEAM) {
-                const int32_t w = ballx[base_new + k];
-                ds += (uint64_t)(row_ptr[w + 1] - row_ptr[w]);
-                ms += to128(sigx[w]);
+                const int32_t w = staged_new ? sm.sv[k] : ballx[base_new + k];
+                const int32_t rs = row_ptr[w], dg = row_ptr[w + 1] - rs;
+                const Sigma m = sigx[w];
+                ds += (uint64_t)dg;
+                ms += to128(m);
+                if (cache_new) {
+                    sm.frs[X][k] = rs;
+                    sm.fdg[X][k] = dg;
+                    sm.fsg[X][k] = m;
+                }
             }
             T::sum_u64_u128(&ds, &ms, sm.red);
+            if (X) fc1 = cache_new; else fc0 = cache_new;
             if (lane == 0) (X ? loff1 : loff0)[lvlx + 2] = fhix + nN;
             if (X) {
                 flo1 = fhi1;

@@ -83,3 +83,19 @@ def test_rhg_mean_degree_and_shape():
     assert abs(g.num_arcs / g.n - 10.0) <= 0.5
     deg = g.degrees()
     assert deg.max() > 20 * deg.mean()  # heavy-tailed
+
+
+def test_serve_trace_deterministic_and_shaped():
+    q1, g1 = G.serve_trace(66, 256, seed=8)
+    q2, g2 = G.serve_trace(66, 256, seed=8)
+    assert q1 == q2 and np.array_equal(g1, g2)
+    assert len(q1) == 256 and g1[0] == 0.0 and np.all(g1[1:] > 0)
+    gi = np.array([q[0] for q in q1])
+    assert gi.min() >= 0 and gi.max() < 66 and len(set(gi.tolist())) > 40
+    assert {q[1] for q in q1} == {0.05, 0.01}
+    assert all(q[2] == 0.1 and q[3] == 16384 for q in q1)
+    assert len({q[4] for q in q1}) == 256  # distinct sampling seeds
+    # unit-rate exponential gaps: mean near 1
+    assert 0.8 < float(np.mean(g1[1:])) < 1.2
+    q3, _ = G.serve_trace(66, 256, seed=9)
+    assert q3 != q1
