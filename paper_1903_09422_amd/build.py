@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkadabra.so")
-SOURCES = [os.path.join(CSRC, "kadabra_kernels.hip"), os.path.join(CSRC, "kadabra_host.cpp")]
+SOURCES = [os.path.join(CSRC, "kadabra_kernels.hip"), os.path.join(CSRC, "kadabra_prep.hip"),
+           os.path.join(CSRC, "kadabra_host.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",

@@ -1,7 +1,8 @@
 // kadabra_host.cpp -- C ABI and host runtime of the gfx950 KADABRA library.
 //
-// Host side: input validation, graph-only preprocessing (components and the
-// vertex-diameter bound, Section 2.3 / Appendix C.1), omega and L, device
+// Host side: input validation, the driver of the graph-only preprocessing on
+// the device (components and the vertex-diameter bound, Section 2.3 /
+// Appendix C.1, kernels in kadabra_prep.hip), omega and L, device
 // memory, and the adaptive loop of Algorithm 1 with checks every N samples
 // (Appendix C.2), driven for any number of concurrent queries:
 //
@@ -146,56 +147,6 @@ int validate_csr(int32_t n, int64_t num_arcs, const int32_t *row_ptr, const int3
     return KADABRA_OK;
 }
 
-// Components (numbered by lowest vertex) and the vertex-diameter bound: per
-// component, BFS from its maximum-degree vertex (lowest id on ties); every
-// shortest path there has at most 2 ecc edges, so VD = max (2 ecc + 1).
-void preprocess(int32_t n, const int32_t *row_ptr, const int32_t *col, std::vector<int32_t> &comp,
-                int32_t *ncomp_out, int32_t *vd_out)
-{
-    comp.assign(n, -1);
-    std::vector<int32_t> queue(n), root;
-    int32_t ncomp = 0;
-    for (int32_t r = 0; r < n; ++r) {
-        if (comp[r] >= 0) continue;
-        size_t head = 0, tail = 0;
-        queue[tail++] = r;
-        comp[r] = ncomp;
-        int32_t best = r;
-        while (head < tail) {
-            const int32_t u = queue[head++];
-            const int32_t du = row_ptr[u + 1] - row_ptr[u], db = row_ptr[best + 1] - row_ptr[best];
-            if (du > db || (du == db && u < best)) best = u;
-            for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
-                if (comp[col[e]] < 0) {
-                    comp[col[e]] = ncomp;
-                    queue[tail++] = col[e];
-                }
-        }
-        root.push_back(best);
-        ++ncomp;
-    }
-    std::vector<int32_t> dist(n, -1);
-    int32_t vd = 1;
-    for (int32_t c = 0; c < ncomp; ++c) {
-        size_t head = 0, tail = 0;
-        queue[tail++] = root[c];
-        dist[root[c]] = 0;
-        int32_t ecc = 0;
-        while (head < tail) {
-            const int32_t u = queue[head++];
-            ecc = std::max(ecc, dist[u]);
-            for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
-                if (dist[col[e]] < 0) {
-                    dist[col[e]] = dist[u] + 1;
-                    queue[tail++] = col[e];
-                }
-        }
-        vd = std::max(vd, 2 * ecc + 1);
-    }
-    *ncomp_out = ncomp;
-    *vd_out = vd;
-}
-
 // omega = ceil(0.5/eps^2 (floor(log2(max(VD - 2, 1))) + 1 + ln(2/delta)))
 int64_t omega_of(int32_t vd, double eps, double delta)
 {
@@ -287,6 +238,80 @@ struct GraphData {
         dev_free(d_comp);
     }
 };
+
+// Components and the vertex-diameter bound on the device (kadabra_prep.hip):
+// per component, a BFS from its maximum-degree vertex (lowest id on ties)
+// reaches everything within ecc levels, and every shortest path there has at
+// most 2 ecc edges, so VD = max (2 ecc + 1) = 2 (deepest level of one BFS from
+// all roots) + 1 (Section 2.3, Appendix C.1).  d_comp receives each vertex's
+// component (its smallest vertex id).
+int gpu_preprocess(GraphData &gd, hipStream_t s)
+{
+    const int32_t n = gd.n;
+    constexpr int32_t kSmallMax = 8192;  // one workgroup runs levels up to this frontier size
+    unsigned long long *key = nullptr;
+    int32_t *dist = nullptr, *q0 = nullptr, *q1 = nullptr, *cnt = nullptr, *host = nullptr;
+    struct Release {
+        std::vector<void *> dev;
+        int32_t **host;
+        ~Release()
+        {
+            for (void *p : dev) dev_free(p);
+            if (*host) (void)hipHostFree(*host);
+        }
+    } rel{{}, &host};
+    HIP_OR_FAIL(alloc_n(&gd.d_comp, (size_t)n));
+    HIP_OR_FAIL(alloc_n(&key, (size_t)n));
+    rel.dev.push_back(key);
+    HIP_OR_FAIL(alloc_n(&dist, (size_t)n));
+    rel.dev.push_back(dist);
+    HIP_OR_FAIL(alloc_n(&q0, (size_t)n));
+    rel.dev.push_back(q0);
+    HIP_OR_FAIL(alloc_n(&q1, (size_t)n));
+    rel.dev.push_back(q1);
+    HIP_OR_FAIL(alloc_n(&cnt, 8));  // [0], [1] queue sizes, [2] components, [4..6] one-workgroup state
+    rel.dev.push_back(cnt);
+    HIP_OR_FAIL(hipHostMalloc((void **)&host, 8 * sizeof(int32_t), hipHostMallocDefault));
+    HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)key, 2 * (size_t)n, 0u, s));
+    HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)cnt, 8, 0u, s));
+    HIP_OR_FAIL(kd::launch_cc(gd.d_row_ptr, gd.d_col, n, gd.d_comp, s));
+    HIP_OR_FAIL(kd::launch_bfs_roots(gd.d_row_ptr, gd.d_comp, n, key, dist, q0, cnt, s));
+    HIP_OR_FAIL(hipMemcpyAsync(host, cnt, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    gd.ncomp = host[2];
+    int32_t fn = host[0], level = 0, which = 0;
+    if (fn != gd.ncomp || fn < 1)
+        return fail(KADABRA_EDEVICE, "preprocessing found %d roots for %d components", fn, gd.ncomp);
+    while (fn > 0) {
+        if (fn <= kSmallMax) {
+            host[4] = fn;
+            host[5] = level;
+            host[6] = which;
+            HIP_OR_FAIL(hipMemcpyAsync(cnt + 4, host + 4, 3 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            HIP_OR_FAIL(kd::launch_bfs_small(gd.d_row_ptr, gd.d_col, dist, q0, q1, cnt + 4, kSmallMax, s));
+            HIP_OR_FAIL(hipMemcpyAsync(host + 4, cnt + 4, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIP_OR_FAIL(hipStreamSynchronize(s));
+            fn = host[4];
+            level = host[5];
+            which = host[6];
+        } else {
+            host[which] = fn;
+            host[which ^ 1] = 0;
+            HIP_OR_FAIL(hipMemcpyAsync(cnt, host, 2 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            HIP_OR_FAIL(kd::launch_bfs_level(gd.d_row_ptr, gd.d_col, which ? q1 : q0, cnt + which, fn, level, dist,
+                                             which ? q0 : q1, cnt + (which ^ 1), s));
+            HIP_OR_FAIL(hipMemcpyAsync(host, cnt, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIP_OR_FAIL(hipStreamSynchronize(s));
+            fn = host[which ^ 1];
+            level += 1;
+            which ^= 1;
+        }
+        if (fn < 0 || fn > n || level > n) return fail(KADABRA_EDEVICE, "preprocessing BFS out of range");
+    }
+    // the frontier emptied after `level` expansions: the deepest level is level - 1
+    gd.vd = 2 * std::max(level - 1, 0) + 1;
+    return KADABRA_OK;
+}
 
 // One adaptive run.
 struct Query {
@@ -1161,22 +1186,19 @@ int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr, co
     gd.n = n;
     gd.arcs = num_arcs;
     gd.max_deg = max_deg;
-    std::vector<int32_t> comp;
-    preprocess(n, row_ptr, col_idx, comp, &gd.ncomp, &gd.vd);
     OK_OR_RETURN(g->runner.init());
     struct {
         int32_t **dst;
         const int32_t *src;
         size_t count;
-    } up[] = {{&gd.d_row_ptr, row_ptr, (size_t)n + 1},
-              {&gd.d_col, col_idx, (size_t)num_arcs},
-              {&gd.d_comp, comp.data(), (size_t)n}};
+    } up[] = {{&gd.d_row_ptr, row_ptr, (size_t)n + 1}, {&gd.d_col, col_idx, (size_t)num_arcs}};
     for (auto &u : up) {
         HIP_OR_FAIL(alloc_n(u.dst, u.count));
         if (u.count) HIP_OR_FAIL(hipMemcpy(*u.dst, u.src, u.count * sizeof(int32_t), hipMemcpyHostToDevice));
     }
     // the graph is read by kernels on non-blocking streams: the uploads land first
     HIP_OR_FAIL(hipDeviceSynchronize());
+    OK_OR_RETURN(gpu_preprocess(gd, g->runner.own_stream));
     *out = g.release();
     return KADABRA_OK;
 }

@@ -109,4 +109,17 @@ hipError_t launch_fill_u32(uint32_t *p, size_t count, uint32_t value, hipStream_
 hipError_t launch_eval_fg(const int32_t *counts, int32_t n, int64_t tau, int64_t omega, double L,
                           double *f, double *g, hipStream_t s);
 
+// Graph preprocessing (kadabra_prep.hip): components as each vertex's
+// component minimum id; BFS from every component's maximum-degree vertex
+// (lowest id on ties).  counters: [0] roots found (the first frontier),
+// [2] components; key must start zeroed.
+hipError_t launch_cc(const int32_t *row_ptr, const int32_t *col, int32_t n, int32_t *parent, hipStream_t s);
+hipError_t launch_bfs_roots(const int32_t *row_ptr, const int32_t *comp, int32_t n, unsigned long long *key,
+                            int32_t *dist, int32_t *frontier, int32_t *counters, hipStream_t s);
+hipError_t launch_bfs_level(const int32_t *row_ptr, const int32_t *col, const int32_t *frontier,
+                            const int32_t *count, int32_t frontier_size, int32_t level, int32_t *dist,
+                            int32_t *next, int32_t *next_count, hipStream_t s);
+hipError_t launch_bfs_small(const int32_t *row_ptr, const int32_t *col, int32_t *dist, int32_t *q0, int32_t *q1,
+                            int32_t *state, int32_t small_max, hipStream_t s);
+
 }  // namespace kd
