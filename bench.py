@@ -382,6 +382,8 @@ PMC_CMDS = {
                   "python3 bench.py --calibrate-copy 1073741824",
     "copy_write": "rocprofv3 --pmc WRITE_SIZE -f csv -d DIR/pmc_copy_WRITE_SIZE -o copy -- "
                   "python3 bench.py --calibrate-copy 1073741824",
+    "l2": "rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum -f csv -d DIR/pmc_tcc -o bench -- "
+          "python3 bench.py --workload {w} --steps 2 --warmup 0 --no-cpu",
 }
 
 
@@ -414,8 +416,21 @@ def ingest_pmc(d: str, workload: str) -> int:
     durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6 for r in trace
             if "sample_kernel" in r["Kernel_Name"]]
     full = [x for x in durs if x > 0.05 * max(durs)]
+    l2 = None
+    if os.path.isdir(os.path.join(d, "pmc_tcc")):
+        hits = kib("pmc_tcc", "bench", "sample_kernel")  # both counters, by row
+        by = {}
+        for r in rows(os.path.join(d, "pmc_tcc", "bench_counter_collection.csv")):
+            if "sample_kernel" in r["Kernel_Name"]:
+                by.setdefault(r["Dispatch_Id"], {})[r["Counter_Name"]] = float(r["Counter_Value"])
+        full_l2 = [v for v in by.values() if v.get("TCC_HIT_sum", 0) + v.get("TCC_MISS_sum", 0) > 1e5]
+        if full_l2 and hits:
+            h = float(np.mean([v["TCC_HIT_sum"] for v in full_l2]))
+            m = float(np.mean([v["TCC_MISS_sum"] for v in full_l2]))
+            l2 = {"hits_per_launch": h, "misses_per_launch": m, "hit_rate": h / (h + m)}
     summary = {
         "kernel": "sample_kernel", "workload": workload, "kernel_source_sha": _kernel_sha(),
+        "l2": l2,
         "hbm_bytes_per_launch": hbm,
         "fetch_kib_per_launch": float(np.mean(fetch)), "write_kib_per_launch": float(np.mean(write)),
         "fetch_factor": fetch_factor, "write_factor": write_factor,
@@ -445,6 +460,10 @@ def ingest_pmc(d: str, workload: str) -> int:
         f.write(f"- WRITE_SIZE per sampling launch: {np.mean(write):.0f} KiB; calibration factor "
                 f"{write_factor:.3f}\n")
         f.write(f"- HBM bytes per launch: {hbm / 1e9:.3f} GB\n")
+        if l2:
+            f.write("\n## L2 (--pmc TCC_HIT_sum TCC_MISS_sum)\n\n")
+            f.write(f"- per sampling launch: {l2['hits_per_launch']:.4g} hits, "
+                    f"{l2['misses_per_launch']:.4g} misses, hit rate {l2['hit_rate']:.3f}\n")
     print(json.dumps(summary))
     return 0
 

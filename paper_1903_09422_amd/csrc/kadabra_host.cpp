@@ -136,13 +136,22 @@ int validate_csr(int32_t n, int64_t num_arcs, const int32_t *row_ptr, const int3
         }
     }
     if (max_deg >= kMaxN) return fail(KADABRA_ERANGE, "degree %d is not below 2^23", max_deg);
-    // symmetry: every arc (v, w) has its reverse (w, v)
+    // symmetry: every arc (v, w) has its reverse (w, v).  Rows are strictly
+    // ascending, so a scan over v upwards meets the sources of the arcs into w
+    // in the order of row w: one cursor per row must find v at each step and
+    // reach the row's end (O(n + m), no search).
+    std::vector<int32_t> cur(row_ptr, row_ptr + n);
     for (int32_t v = 0; v < n; ++v)
         for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
             const int32_t w = col[e];
-            if (!std::binary_search(col + row_ptr[w], col + row_ptr[w + 1], v))
+            const int32_t t = cur[(size_t)w]++;
+            if (t >= row_ptr[w + 1] || col[t] != v)
                 return fail(KADABRA_EINVAL, "arc (%d, %d) has no reverse: graph not undirected", v, w);
         }
+    for (int32_t w = 0; w < n; ++w)
+        if (cur[(size_t)w] != row_ptr[w + 1])
+            return fail(KADABRA_EINVAL, "arc (%d, %d) has no reverse: graph not undirected", w,
+                        col[cur[(size_t)w]]);
     *max_deg_out = max_deg;
     return KADABRA_OK;
 }
