@@ -156,7 +156,13 @@ struct Team {
         return v;
     }
 
-    // sum over the team (result in every lane); red: >= WAVES words of LDS
+    // Team reductions: result in every lane.  A reduction has one barrier,
+    // before it reads the per-wavefront words in red; it does not wait for
+    // those reads to finish, so consecutive reductions must use different red
+    // buffers (the next reduction's barrier then guarantees the reads of the
+    // one before it are done).  red: >= 4 WAVES words of LDS.
+    //
+    // sum over the team
     __device__ static uint64_t sum_u64(uint64_t v, uint64_t *red)
     {
         v = wave_sum(v);
@@ -167,7 +173,6 @@ struct Team {
         uint64_t t = 0;
 #pragma unroll
         for (int k = 0; k < WAVES; ++k) t += red[k];
-        __syncthreads();
         return t;
     }
 
@@ -189,7 +194,6 @@ struct Team {
         u128 t = 0;
 #pragma unroll
         for (int k = 0; k < WAVES; ++k) t += ((u128)red[2 * k + 1] << 64) | red[2 * k];
-        __syncthreads();
         return t;
     }
 
@@ -224,7 +228,6 @@ struct Team {
             tx += red[3 * k];
             tb += ((u128)red[3 * k + 2] << 64) | red[3 * k + 1];
         }
-        __syncthreads();
         *a = tx;
         *b = tb;
     }
@@ -251,7 +254,6 @@ struct Team {
             const u128 x = ((u128)red[2 * k + 1] << 64) | red[2 * k];
             t = x > t ? x : t;
         }
-        __syncthreads();
         return t;
     }
 
@@ -283,7 +285,6 @@ struct Team {
             x.hi = ((u128)red[4 * k + 3] << 64) | red[4 * k + 2];
             if (x.hi > t.hi || (x.hi == t.hi && x.lo > t.lo)) t = x;
         }
-        __syncthreads();
         return t;
     }
 
@@ -311,7 +312,6 @@ struct Team {
             off += (k < w) ? t : 0;
             tot += t;
         }
-        __syncthreads();
         *total = tot;
         return off + x - v;
     }
@@ -344,7 +344,6 @@ struct Team {
             off += (k < w) ? t : (u128)0;
             tot += t;
         }
-        __syncthreads();
         *total = tot;
         return off + x - v;
     }
@@ -409,11 +408,12 @@ struct SampleShared {
     int32_t frs[2][TEAM];
     int32_t fdg[2][TEAM];
     Sigma fsg[2][TEAM];
-    uint64_t red[4 * (TEAM / 64) < 16 ? 16 : 4 * (TEAM / 64)];  // team reduction scratch (4 words a wave)
+    uint64_t red[2][4 * (TEAM / 64) < 16 ? 16 : 4 * (TEAM / 64)];  // reduction scratch, used alternately
     uint64_t acc[ST_COUNT];           // work counters of the query being served (lane 0)
     int64_t claim;                    // claimed launch-wide sample index
     int32_t query;                    // its query
-    int32_t nnext, nmeet, pick, ncand;
+    int32_t nnext[2], nmeet[2];       // append counters of a level, used alternately
+    int32_t pick, ncand;
 };
 
 // A const int32 in the global address space, and the cast to it.
@@ -457,6 +457,12 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
     constexpr int STAGE = Cap<TEAM>::STAGE;
     __shared__ SampleShared<TEAM> sm;
     const int lane = threadIdx.x;
+    // Reduction scratch: a reduction does not wait for its reads of red to
+    // finish, so a buffer is reused only after a barrier.  Each call site below
+    // names its buffer so that this holds: redA where a barrier follows anyway,
+    // redB for a reduction directly followed by another one.
+    uint64_t *const redA = sm.red[0];
+    uint64_t *const redB = sm.red[1];
     const size_t ns = (size_t)a.st.nstride;
     const size_t slot = blockIdx.x;
     uint32_t *const code = a.st.code + slot * (size_t)a.st.code_stride;
@@ -562,6 +568,8 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
             loff0[1] = 1;
             loff1[0] = 0;
             loff1[1] = 1;
+            sm.nnext[0] = sm.nnext[1] = 0;
+            sm.nmeet[0] = sm.nmeet[1] = 0;
         }
         // per-side BFS state (uniform across the team; side X selected by value)
         int32_t lvl0 = 0, lvl1 = 0;
@@ -581,6 +589,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
         int X = 0, nN = 0, nM = 0;
         int fail_site = 0;
         bool ok = true, retry = false;
+        int lp = 0;  // which append counters this BFS iteration uses (the other ones are zero)
         T::sync();
         for (;;) {
             X = (dsum0 <= dsum1) ? 0 : 1;  // cheaper side; s on ties
@@ -610,17 +619,14 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
             const bool want_probe = (probe_min >= 0) ? (dsx >= probe_min)
                                                      : (dsx * dsy >= 4 * num_arcs);
             const bool probe = !retry && want_probe && bitw128(X ? fmass1 : fmass0) <= SIGMA_BITS;
-            if (lane == 0) {
-                if (!retry) {
-                    sm.acc[ST_VEXP] += (uint64_t)(fhix - flox);
-                    sm.acc[ST_ESCAN] += (uint64_t)dsx;
-                }
-                sm.nnext = 0;
-                sm.nmeet = 0;
+            if (lane == 0 && !retry) {
+                sm.acc[ST_VEXP] += (uint64_t)(fhix - flox);
+                sm.acc[ST_ESCAN] += (uint64_t)dsx;
             }
             const uint32_t code_new = level_code(lvlx + 1);  // code of the new level
             const int32_t base_new = fhix;
-            __syncthreads();
+            int32_t *const cnt_new = &sm.nnext[lp];
+            int32_t *const cnt_meet = &sm.nmeet[lp];
             const bool fcx = X ? fc1 : fc0;  // then the frontier is one chunk
             for (int32_t c0 = flox; c0 < fhix; c0 += TEAM) {
                 const int32_t idx = c0 + lane;
@@ -639,7 +645,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     }
                 }
                 int32_t tot;
-                const int32_t ex = T::excl_scan_i32(dg, &tot, sm.red);
+                const int32_t ex = T::excl_scan_i32(dg, &tot, redA);
                 sm.cpfx[lane] = ex;
                 const int32_t cnt = min(TEAM, fhix - c0);
                 __syncthreads();
@@ -707,13 +713,13 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                             claimed = (o == 0u);
                             dxc[k] = claimed ? code_new : o;
                         }
-                        const int p = wave_append(claimed, &sm.nnext);
+                        const int p = wave_append(claimed, cnt_new);
                         if (claimed) {
                             ballx[base_new + p] = w;
                             if (p < STAGE) sm.sv[p] = w;
                         }
                         const bool is_meet = claimed && dyc[k] != 0u;
-                        const int q = wave_append(is_meet, &sm.nmeet);
+                        const int q = wave_append(is_meet, cnt_meet);
                         if (is_meet) meet[q] = w;
                         add[k] = (k == 0 || e + k * TEAM < tot) && dxc[k] == code_new;
                     }
@@ -736,11 +742,17 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 __syncthreads();
             }
             PHASE_MARK(1);
-            nN = uniform_i32(sm.nnext);
-            nM = uniform_i32(sm.nmeet);
+            nN = uniform_i32(*cnt_new);
+            nM = uniform_i32(*cnt_meet);
+            // the next iteration counts in the other pair, last read before this
+            // iteration's barriers
+            if (lane == 0) {
+                sm.nnext[lp ^ 1] = 0;
+                sm.nmeet[lp ^ 1] = 0;
+            }
+            lp ^= 1;
             if (probe && nM == 0) {  // no meeting on this level: expand it in full
                 retry = true;
-                T::sync();  // every wave has read the counters before they are reset
                 continue;
             }
             retry = false;
@@ -757,7 +769,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     const u128 v = to128(sigx[ballx[base_new + k]]);
                     hm = v > hm ? v : hm;
                 }
-                hm = T::max_u128(hm, sm.red);
+                hm = T::max_u128(hm, redA);
                 const int sh = bitw128(hm) - SIGMA_BITS;
                 if (sh > 0) {
                     const u128 add = ((u128)1 << sh) - 1;
@@ -788,7 +800,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     sm.fsg[X][k] = m;
                 }
             }
-            T::sum_u64_u128(&ds, &ms, sm.red);
+            T::sum_u64_u128(&ds, &ms, redB);
             if (X) fc1 = cache_new; else fc0 = cache_new;
             if (lane == 0) (X ? loff1 : loff0)[lvlx + 2] = fhix + nN;
             if (X) {
@@ -823,7 +835,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     const U256 p = mul_128x128(to128(sig0[w]), to128(sig1[w]));
                     if (p.hi > pm.hi || (p.hi == pm.hi && p.lo > pm.lo)) pm = p;
                 }
-                pm = T::max_u256(pm, sm.red);
+                pm = T::max_u256(pm, redA);
                 const int shp = max(0, bitw256(pm) - WEIGHT_BITS);
                 uint64_t tot = 0;
                 int32_t vmin = nv, vmax = -1;
@@ -841,7 +853,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     vmin = min(vmin, w);
                     vmax = max(vmax, w);
                 }
-                tot = T::sum_u64(tot, sm.red);
+                tot = T::sum_u64(tot, redB);
                 // team min / max of the ids (as maxima of n - id and id + 1),
                 // needed by the binary search over ids only
                 uint64_t mn = (uint64_t)(uint32_t)(nv - vmin), mx = (uint64_t)(uint32_t)(vmax + 1);
@@ -851,17 +863,17 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     mx = max(mx, (uint64_t)__shfl_xor(mx, o, 64));
                 }
                 if (T::WAVES > 1 && nM > TEAM) {
+                    uint64_t *const rr = redA;  // then a sync
                     const int wv = lane >> 6;
                     if ((lane & 63) == 0) {
-                        sm.red[2 * wv] = mn;
-                        sm.red[2 * wv + 1] = mx;
+                        rr[2 * wv] = mn;
+                        rr[2 * wv + 1] = mx;
                     }
                     __syncthreads();
                     for (int k = 0; k < T::WAVES; ++k) {
-                        mn = max(mn, sm.red[2 * k]);
-                        mx = max(mx, sm.red[2 * k + 1]);
+                        mn = max(mn, rr[2 * k]);
+                        mx = max(mx, rr[2 * k + 1]);
                     }
-                    __syncthreads();
                 }
                 T::sync();  // staged weights visible to the whole team
                 const uint64_t r = __umul64hi(philox_u64(seed, (uint64_t)i, 1u), tot);
@@ -878,6 +890,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 } else {
                     // smallest id v whose inclusive prefix (ascending ids) exceeds r
                     int32_t lo = nv - (int32_t)mn, hi = (int32_t)mx - 1;
+                    int32_t it = 0;  // consecutive sums alternate their scratch
                     while (lo < hi) {
                         const int32_t mid = lo + ((hi - lo) >> 1);
                         uint64_t part = 0;
@@ -888,7 +901,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                             for (int32_t k = lane; k < nM; k += TEAM)
                                 part += (meet[k] <= mid) ? meetw[k] : 0u;
                         }
-                        part = T::sum_u64(part, sm.red);
+                        part = T::sum_u64(part, (it++ & 1) ? redB : redA);
                         if (part > r) hi = mid; else lo = mid + 1;
                     }
                     v = lo;
@@ -942,7 +955,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                         if (nc <= STAGE) {
                             u128 part = 0;
                             for (int32_t k = lane; k < nc; k += TEAM) part += to128(sm.sw[k]);
-                            const u128 tot = T::sum_u128(part, sm.red);
+                            const u128 tot = T::sum_u128(part, redA);
                             const u128 r = mulhi_64x128(U, tot);
                             pick_by_id_prefix<TEAM>(sm.sv, sm.sw, nc, r, &sm.pick);
                             done = true;
@@ -971,7 +984,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                                 part += to128(sg[p]);
                         }
                         u128 tot;
-                        const u128 ex_pre = T::excl_scan_u128(part, &tot, sm.red);
+                        const u128 ex_pre = T::excl_scan_u128(part, &tot, redA);
                         const u128 r = mulhi_64x128(U, tot);
                         if (part != 0 && ex_pre <= r && r < ex_pre + part) {
                             u128 acc = ex_pre;
