@@ -100,6 +100,10 @@ int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr,
  *                     degree sums reaches four times the arc count.
  *   "test_fail_alloc" k >= 1: the k-th device allocation of the next run's
  *                     buffers fails with ENOMEM (failure-path testing); 0: off.
+ *   "test_level_cap"  k >= 3: the sampler is given room for only k BFS levels
+ *                     per side, so samples needing more fail its level-bound
+ *                     check and the run ends with EDEVICE (failure-path
+ *                     testing of device-side checks); 0 (default): off.
  * Errors: EINVAL (unknown key or value out of range).
  */
 int kadabra_set_param(kadabra_graph *g, const char *key, int64_t value);
@@ -184,7 +188,8 @@ typedef struct kadabra_batch kadabra_batch;
 int kadabra_batch_create(kadabra_batch **out);
 
 /* As kadabra_set_param for the batch's mapping ("team", "slots", "frames",
- * "overlap", "probe_min", "test_fail_alloc"); "check_interval" is per query. */
+ * "overlap", "probe_min", "test_fail_alloc", "test_level_cap"); "check_interval" is per
+ * query. */
 int kadabra_batch_set_param(kadabra_batch *b, const char *key, int64_t value);
 int kadabra_batch_get_param(const kadabra_batch *b, const char *key, int64_t *value);
 int kadabra_batch_set_stream(kadabra_batch *b, void *hip_stream);

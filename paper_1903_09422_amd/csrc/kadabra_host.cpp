@@ -187,6 +187,7 @@ struct Params {
     int overlap = 1;
     int64_t probe_min = -1;  // -1 auto rule
     int64_t fail_alloc = 0;  // test hook
+    int32_t level_cap = 0;   // test hook: 0, or a smaller level capacity per side
 };
 
 int set_common_param(Params &p, const char *key, int64_t value, bool *known)
@@ -214,6 +215,10 @@ int set_common_param(Params &p, const char *key, int64_t value, bool *known)
     } else if (!strcmp(key, "test_fail_alloc")) {
         if (value < 0) return fail(KADABRA_EINVAL, "test_fail_alloc must be >= 0");
         p.fail_alloc = value;
+    } else if (!strcmp(key, "test_level_cap")) {
+        if (value != 0 && (value < 3 || value > (1 << 20)))
+            return fail(KADABRA_EINVAL, "test_level_cap must be 0 or in [3, 2^20]");
+        p.level_cap = (int32_t)value;
     } else {
         *known = false;
     }
@@ -228,6 +233,7 @@ int get_common_param(const Params &p, const char *key, int64_t *value)
     else if (!strcmp(key, "frames")) *value = p.frames;
     else if (!strcmp(key, "overlap")) *value = p.overlap;
     else if (!strcmp(key, "probe_min")) *value = p.probe_min;
+    else if (!strcmp(key, "test_level_cap")) *value = p.level_cap;
     else return 1;
     return 0;
 }
@@ -679,6 +685,9 @@ int Runner::run(std::vector<Query *> &queries, const Params &p,
         sa.claim = d_claim;
         sa.claim_base = claim_next;
         sa.st = st;
+        // test hook: a smaller level capacity trips the sampler's level-bound
+        // check (the level offsets of a slot then pack into a smaller stride)
+        if (p.level_cap > 0 && p.level_cap < st.lcap) sa.st.lcap = p.level_cap;
         claim_next += (uint64_t)total + (uint64_t)slots;  // every block makes one failing claim
         L.e0 = take_event();
         L.e1 = take_event();

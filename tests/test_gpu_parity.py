@@ -203,6 +203,33 @@ def test_errors_and_state():
         assert_same(dev.result(), oracle.run(g, 0.1, 0.1, 1, 1024))
 
 
+def test_device_check_failure_reported_and_recoverable():
+    """A device-side check that fails (forced from the host: room for only 3 BFS
+    levels per side) ends the run with EDEVICE naming the check; the handle
+    stays usable and its next run equals the oracle."""
+    g = G.path_graph(40)
+    print("case device check failure", flush=True)
+    want = oracle.run(g, 0.1, 0.1, 3, 64)
+    with Graph.from_csr(g) as dev:
+        dev.set_param("check_interval", 64)
+        dev.set_param("test_level_cap", 3)
+        assert dev.get_param("test_level_cap") == 3
+        with pytest.raises(KadabraError) as e:
+            dev.run(0.1, 0.1, 3)
+        assert e.value.status == _lib.EDEVICE
+        assert "vertex-diameter bound" in str(e.value) and "seed 3" in str(e.value)
+        with pytest.raises(KadabraError) as e:
+            dev.result()
+        assert e.value.status == _lib.ESTATE
+        dev.set_param("test_level_cap", 0)
+        dev.run(0.1, 0.1, 3)
+        assert_same(dev.result(), want)
+    with Graph.from_csr(g) as dev:
+        for bad in (1, 2, -1):
+            with pytest.raises(KadabraError):
+                dev.set_param("test_level_cap", bad)
+
+
 def test_cancel_from_another_thread():
     g, _, _, _ = G.workload("pgrid1024")
     print("case cancel", flush=True)

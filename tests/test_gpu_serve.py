@@ -167,3 +167,23 @@ def test_serve_errors_and_shutdown():
         t0 = time.time()
         srv.close()
         assert time.time() - t0 < 30.0
+
+
+def test_serve_device_failure_stops_server():
+    """A device-side check failure (forced: room for 3 BFS levels) fails the
+    queries in flight with EDEVICE, and the server then refuses new work."""
+    g = G.path_graph(60)
+    print("case serve device failure", flush=True)
+    with Graph.from_csr(g) as h:
+        with Server([h]) as srv:
+            srv.set_param("test_level_cap", 3)
+            t = srv.submit(0, 0.1, 0.1, 1, 32)
+            assert srv.wait(t, timeout=60.0)
+            with pytest.raises(KadabraError) as e:
+                srv.result(t, 0)
+            assert e.value.status == _lib.EDEVICE
+            assert srv.info()["failed"] == 1
+            with pytest.raises(KadabraError) as e:
+                srv.submit(0, 0.1, 0.1, 2, 32)
+            assert e.value.status == _lib.EDEVICE
+            srv.release(t)
