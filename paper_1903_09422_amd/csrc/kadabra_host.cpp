@@ -559,10 +559,18 @@ struct Runner {
             const std::function<void(std::vector<Query *> &)> &admit = nullptr,
             int64_t sample_cap = -1, int64_t *fail_countdown = nullptr,
             const std::function<void(Query *)> &on_done = nullptr);
+
+  private:
+    std::vector<Query *> live_;  // queries the current run has started
+    int run_rounds(std::vector<Query *> &queries, const Params &p,
+                   const std::function<void(std::vector<Query *> &)> &admit, int64_t sample_cap,
+                   int64_t *fail_countdown, const std::function<void(Query *)> &on_done);
 };
 
 int Runner::start_query(Query &q, int64_t *fc)
 {
+    q.done = false;  // from here on the runner owns the query until finish_query
+    q.status = KADABRA_OK;
     const size_t n = (size_t)q.gd->n;
     if (!q.counts) HIP_OR_FAIL(alloc_n(&q.counts, n, fc));
     if (q.frames_len != 2 * (size_t)q.nframes * n) {
@@ -607,9 +615,27 @@ int Runner::run(std::vector<Query *> &queries, const Params &p,
                 const std::function<void(std::vector<Query *> &)> &admit, int64_t sample_cap,
                 int64_t *fail_countdown, const std::function<void(Query *)> &on_done)
 {
+    live_.clear();
+    const int rc = run_rounds(queries, p, admit, sample_cap, fail_countdown, on_done);
+    // a run that ended early (a failed device call) still returns every
+    // control block and marks its unfinished queries failed
+    for (Query *q : live_)
+        if (!q->done) {
+            if (q->status == KADABRA_OK) q->status = rc != KADABRA_OK ? rc : KADABRA_EDEVICE;
+            finish_query(*q);
+        }
+    live_.clear();
+    return rc;
+}
+
+int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
+                       const std::function<void(std::vector<Query *> &)> &admit, int64_t sample_cap,
+                       int64_t *fail_countdown, const std::function<void(Query *)> &on_done)
+{
     std::vector<Query *> active;
     auto take_new = [&](std::vector<Query *> &incoming) -> int {
         for (Query *q : incoming) {
+            live_.push_back(q);
             OK_OR_RETURN(start_query(*q, fail_countdown));
             active.push_back(q);
         }
@@ -807,13 +833,19 @@ int Runner::run(std::vector<Query *> &queries, const Params &p,
                 if (q->status == KADABRA_OK) q->status = status;
                 finished.push_back(q);
             }
+        // a finished query leaves every list of the runner before on_done hands
+        // it back: its owner may free it from then on
         for (Query *q : finished) {
             for (Launch &L : pend)
                 for (auto &it : L.items)
                     if (it.first == q) it.first = nullptr;
             finish_query(*q);
-            if (on_done) on_done(q);
         }
+        if (!finished.empty())
+            live_.erase(std::remove_if(live_.begin(), live_.end(), [](const Query *q) { return q->done; }),
+                        live_.end());
+        if (on_done)
+            for (Query *q : finished) on_done(q);
         if (status != KADABRA_OK) break;
         active.swap(still);
         if (admit) {

@@ -203,6 +203,31 @@ def test_errors_and_state():
         assert_same(dev.result(), oracle.run(g, 0.1, 0.1, 1, 1024))
 
 
+def test_allocation_failure_at_every_point():
+    """The k-th device allocation of a first run fails (k = 1, 2, ...: the
+    sample pool, launch tables, control blocks, per-query buffers): the run
+    returns ENOMEM and leaves no result, and the same handle's next run equals
+    the oracle; past the last allocation the run simply succeeds."""
+    g = G.erdos_renyi(300, 5.0, seed=8)
+    want = oracle.run(g, 0.1, 0.1, 2, 256)
+    print("case allocation failure sweep", flush=True)
+    failures = 0
+    for k in range(1, 60):
+        with Graph.from_csr(g) as dev:
+            dev.set_param("check_interval", 256)
+            dev.set_param("test_fail_alloc", k)
+            try:
+                dev.run(0.1, 0.1, 2)
+            except KadabraError as e:
+                assert e.status == _lib.ENOMEM
+                failures += 1
+                with pytest.raises(KadabraError):
+                    dev.result()
+                dev.run(0.1, 0.1, 2)
+            assert_same(dev.result(), want)
+    assert 5 < failures < 59  # every allocation point was hit, then the runs succeed
+
+
 def test_device_check_failure_reported_and_recoverable():
     """A device-side check that fails (forced from the host: room for only 3 BFS
     levels per side) ends the run with EDEVICE naming the check; the handle
