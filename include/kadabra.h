@@ -272,7 +272,8 @@ int kadabra_server_submit(kadabra_server *s, int32_t graph_index, double eps, do
                           int64_t check_interval, int64_t *ticket);
 
 /* Blocks until the ticket's query is final or timeout_s seconds pass
- * (timeout_s < 0: no limit); *done = 1 if final.  Errors: EINVAL (ticket). */
+ * (timeout_s < 0: no limit); *done = 1 if final.  Errors: EINVAL (unknown
+ * ticket, or released by another thread while waiting). */
 int kadabra_server_wait(kadabra_server *s, int64_t ticket, double timeout_s, int32_t *done);
 
 /*
@@ -286,8 +287,9 @@ int kadabra_server_result(kadabra_server *s, int64_t ticket, double *scores, int
                           kadabra_stats *stats, double *latency_ms);
 
 /* Returns a final query's device memory to the server (the ticket becomes
- * invalid).  Call it after the last kadabra_server_result on the ticket has
- * returned.  Errors: EINVAL (ticket), ESTATE (not final yet). */
+ * invalid).  Results of one ticket may be read from several threads at once;
+ * a release while a read is in progress is refused.  Errors: EINVAL (ticket),
+ * ESTATE (not final yet, or a result read in progress). */
 int kadabra_server_release(kadabra_server *s, int64_t ticket);
 
 /* Counters and latency percentiles; reset = 1 restarts the latency window. */

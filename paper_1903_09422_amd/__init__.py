@@ -223,6 +223,7 @@ class Server:
         check(lib().kadabra_server_create(arr, len(self._graphs), int(hbm_budget_bytes),
                                           int(max_active), C.byref(h)))
         self._h = h
+        self._graph_of = {}  # ticket -> graph index (sizes the result buffers)
 
     def set_param(self, key: str, value: int) -> None:
         check(lib().kadabra_server_set_param(self._h, key.encode(), int(value)))
@@ -237,6 +238,7 @@ class Server:
         t = C.c_int64()
         check(lib().kadabra_server_submit(self._h, int(graph_index), float(eps), float(delta),
                                           int(seed), int(check_interval), C.byref(t)))
+        self._graph_of[int(t.value)] = int(graph_index)
         return int(t.value)
 
     def wait(self, ticket: int, timeout: float = -1.0) -> bool:
@@ -244,8 +246,10 @@ class Server:
         check(lib().kadabra_server_wait(self._h, int(ticket), float(timeout), C.byref(done)))
         return bool(done.value)
 
-    def result(self, ticket: int, graph_index: int, scores: bool = True):
+    def result(self, ticket: int, graph_index: int = None, scores: bool = True):
         """(RunResult, latency in ms) of a final query."""
+        if graph_index is None:
+            graph_index = self._graph_of.get(int(ticket), 0)  # an unknown ticket: the library reports it
         n = self._graphs[graph_index].n
         sc = np.empty(n, dtype=np.float64) if scores else None
         counts = np.empty(n, dtype=np.int32)
@@ -259,6 +263,7 @@ class Server:
 
     def release(self, ticket: int) -> None:
         check(lib().kadabra_server_release(self._h, int(ticket)))
+        self._graph_of.pop(int(ticket), None)
 
     def info(self, reset: bool = False) -> dict:
         inf = ServerInfo()

@@ -888,6 +888,7 @@ struct Served : Query {
     int64_t frame_bytes = 0;   // part of the charge returned when sampling ends
     bool admitted = false;
     bool final_ = false;
+    int readers = 0;           // result reads in progress (release waits for none)
     std::string err;
     std::chrono::steady_clock::time_point t_admit;
     double latency_ms = 0.0;
@@ -1619,12 +1620,18 @@ int kadabra_server_wait(kadabra_server *s, int64_t ticket, double timeout_s, int
 {
     if (!s) return fail(KADABRA_EINVAL, "null handle");
     std::unique_lock<std::mutex> lk(s->mu);
+    if (s->tickets.find(ticket) == s->tickets.end())
+        return fail(KADABRA_EINVAL, "unknown ticket %lld", (long long)ticket);
+    // the ticket is looked up again at every wake-up: another thread may release it
+    auto ready = [s, ticket] {
+        auto it = s->tickets.find(ticket);
+        return it == s->tickets.end() || it->second->final_;
+    };
+    if (timeout_s < 0) s->cv_done.wait(lk, ready);
+    else s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready);
     auto it = s->tickets.find(ticket);
-    if (it == s->tickets.end()) return fail(KADABRA_EINVAL, "unknown ticket %lld", (long long)ticket);
-    Served *v = it->second.get();
-    if (timeout_s < 0) s->cv_done.wait(lk, [v] { return v->final_; });
-    else s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), [v] { return v->final_; });
-    if (done) *done = v->final_ ? 1 : 0;
+    if (it == s->tickets.end()) return fail(KADABRA_EINVAL, "ticket %lld was released while waiting", (long long)ticket);
+    if (done) *done = it->second->final_ ? 1 : 0;
     return KADABRA_OK;
 }
 
@@ -1639,9 +1646,17 @@ int kadabra_server_result(kadabra_server *s, int64_t ticket, double *scores, int
         if (it == s->tickets.end()) return fail(KADABRA_EINVAL, "unknown ticket %lld", (long long)ticket);
         v = it->second.get();
         if (!v->final_) return fail(KADABRA_ESTATE, "ticket %lld is not final", (long long)ticket);
+        if (v->status != KADABRA_OK) return fail(v->status, "%s", v->err.c_str());
+        // the score buffer is made here, once, so concurrent reads share it
+        if (scores && !v->scores) HIP_OR_FAIL(alloc_n(&v->scores, (size_t)v->gd->n));
+        v->readers += 1;  // pinned: release refuses while a read is in progress
     }
-    if (v->status != KADABRA_OK) return fail(v->status, "%s", v->err.c_str());
-    OK_OR_RETURN(read_result(*v, s->io, scores, counts));
+    const int rc = read_result(*v, s->io, scores, counts);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        v->readers -= 1;
+    }
+    OK_OR_RETURN(rc);
     if (stats) fill_stats(*v, v->latency_ms, stats);
     if (latency_ms) *latency_ms = v->latency_ms;
     return KADABRA_OK;
@@ -1655,6 +1670,7 @@ int kadabra_server_release(kadabra_server *s, int64_t ticket)
     if (it == s->tickets.end()) return fail(KADABRA_EINVAL, "unknown ticket %lld", (long long)ticket);
     Served *v = it->second.get();
     if (!v->final_) return fail(KADABRA_ESTATE, "ticket %lld is not final", (long long)ticket);
+    if (v->readers > 0) return fail(KADABRA_ESTATE, "ticket %lld has a result read in progress", (long long)ticket);
     if (v->admitted) {
         const size_t n = (size_t)v->gd->n;
         s->put_bin(v->counts, n * sizeof(int32_t));

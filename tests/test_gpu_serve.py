@@ -187,3 +187,45 @@ def test_serve_device_failure_stops_server():
                 srv.submit(0, 0.1, 0.1, 2, 32)
             assert e.value.status == _lib.EDEVICE
             srv.release(t)
+
+
+def test_serve_concurrent_reads_and_release():
+    """Result reads of one ticket from several threads race with its release:
+    a read returns the same counters or, once released, EINVAL; a release
+    during a read is refused with ESTATE and succeeds afterwards."""
+    g, eps, n_check = MIX[0]
+    print("case serve concurrent reads", flush=True)
+    with Graph.from_csr(g) as h, Server([h]) as srv:
+        t = srv.submit(0, eps, 0.1, 9, n_check)
+        assert srv.wait(t, timeout=60.0)
+        want, _ = srv.result(t)
+        errors = []
+
+        def reader():
+            for _ in range(40):
+                try:
+                    got, _ = srv.result(t)
+                    if not np.array_equal(got.counts, want.counts):
+                        errors.append("counters differ")
+                except KadabraError as e:
+                    if e.status != _lib.EINVAL:
+                        errors.append(e)
+                    return
+
+        ths = [threading.Thread(target=reader) for _ in range(3)]
+        for x in ths:
+            x.start()
+        refused = 0
+        while True:
+            try:
+                srv.release(t)
+                break
+            except KadabraError as e:
+                assert e.status == _lib.ESTATE
+                refused += 1
+        for x in ths:
+            x.join()
+        assert not errors, errors
+        with pytest.raises(KadabraError) as e:
+            srv.result(t)
+        assert e.value.status == _lib.EINVAL
