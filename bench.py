@@ -69,6 +69,7 @@ def main() -> int:
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--frames", type=int, default=1)
     ap.add_argument("--overlap", type=int, default=1)
+    ap.add_argument("--epochs-per-launch", type=int, default=2)
     ap.add_argument("--probe-min", type=int, default=-1)
     ap.add_argument("--cpu-repeats", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
@@ -115,6 +116,7 @@ def main() -> int:
     dev.set_param("slots", args.slots)
     dev.set_param("frames", args.frames)
     dev.set_param("overlap", args.overlap)
+    dev.set_param("epochs_per_launch", args.epochs_per_launch)
     dev.set_param("probe_min", args.probe_min)
     stream = torch.cuda.Stream()
     dev.set_stream(stream)
@@ -172,6 +174,7 @@ def main() -> int:
             "omega": int(st["omega"]),
             "mapping": {"team": dev.get_param("last_team"), "slots": dev.get_param("last_slots"),
                         "frames": args.frames, "overlap": args.overlap,
+                        "epochs_per_launch": args.epochs_per_launch,
                         "probe_min": args.probe_min},
         },
         "traversed_edges_per_s": escan / dt,

@@ -93,6 +93,10 @@ int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr,
  *                     spread over, merged at every boundary.  Default 1.
  *   "overlap"         1: launch the next epoch's samples before the host has
  *                     read the current check (discarded if it stops); 0: no.
+ *   "epochs_per_launch" E in [1, 4]: one sampling launch carries E consecutive
+ *                     check intervals; each boundary is still merged and
+ *                     checked on exactly its own samples (the samples of later
+ *                     intervals of a run that stops are discarded).  Default 2.
  *                     Default 1.
  *   "probe_min"       k >= 0: expansions scanning at least k arcs first look
  *                     for the meeting set without materialising the new level;
@@ -250,10 +254,11 @@ typedef struct {
  * Creates a server over graphs[0 .. ngraphs) (handles from
  * kadabra_create_graph; they must outlive the server and not be destroyed
  * meanwhile; their own runs stay independent).  hbm_budget_bytes bounds the
- * device memory of admitted queries (per query: counters 4n, score buffer 8n,
- * and while sampling the epoch frames 8n * frames bytes); 0 takes half of the
- * device memory free after the sample pool is sized.  max_active bounds the
- * queries in one launch (0: 256).  Errors: EINVAL, ENOMEM, EDEVICE.
+ * device memory of admitted queries (per query: counters 4n, score buffer
+ * 8n, and while sampling the frame sets 8n * frames * epochs_per_launch
+ * bytes); 0 takes half of the device memory free after the sample pool is
+ * sized.  max_active bounds the queries in one launch (0: 256).
+ * Errors: EINVAL, ENOMEM, EDEVICE.
  */
 int kadabra_server_create(const kadabra_graph *const *graphs, int32_t ngraphs, int64_t hbm_budget_bytes,
                           int32_t max_active, kadabra_server **out);

@@ -185,6 +185,7 @@ struct Params {
     int64_t slots = 0;       // 0 auto
     int frames = 1;
     int overlap = 1;
+    int epochs = 2;          // epochs (check intervals) per sampling launch, 1..4
     int64_t probe_min = -1;  // -1 auto rule
     int64_t fail_alloc = 0;  // test hook
     int32_t level_cap = 0;   // test hook: 0, or a smaller level capacity per side
@@ -209,6 +210,10 @@ int set_common_param(Params &p, const char *key, int64_t value, bool *known)
     } else if (!strcmp(key, "overlap")) {
         if (value != 0 && value != 1) return fail(KADABRA_EINVAL, "overlap must be 0 or 1");
         p.overlap = (int)value;
+    } else if (!strcmp(key, "epochs_per_launch")) {
+        if (value < 1 || value > kd::kMaxSets / 2)
+            return fail(KADABRA_EINVAL, "epochs_per_launch must be in [1, %d]", kd::kMaxSets / 2);
+        p.epochs = (int)value;
     } else if (!strcmp(key, "probe_min")) {
         if (value < -1) return fail(KADABRA_EINVAL, "probe_min must be >= -1");
         p.probe_min = value;
@@ -232,6 +237,7 @@ int get_common_param(const Params &p, const char *key, int64_t *value)
     else if (!strcmp(key, "slots")) *value = p.slots;
     else if (!strcmp(key, "frames")) *value = p.frames;
     else if (!strcmp(key, "overlap")) *value = p.overlap;
+    else if (!strcmp(key, "epochs_per_launch")) *value = p.epochs;
     else if (!strcmp(key, "probe_min")) *value = p.probe_min;
     else if (!strcmp(key, "test_level_cap")) *value = p.level_cap;
     else return 1;
@@ -335,18 +341,21 @@ struct Query {
     uint64_t seed = 0;
     int64_t N = 1024;
     int nframes = 1;
+    int epl = 1;                // epochs per sampling launch
+    int nsets = 2;              // frame sets, 2 epl: epoch e uses set e mod nsets
     int64_t probe_min = -1;
     int64_t omega = 0;
     double L = 0;
     // device buffers
     int32_t *counts = nullptr;
-    int32_t *frames = nullptr;  // [2][nframes][n]
+    int32_t *frames = nullptr;  // [nsets][nframes][n]
     size_t frames_len = 0;
     double *scores = nullptr;
     int cslot = -1;             // control block index in the runner
     // progress
     int64_t k = 0;              // epochs whose samplers were launched
     int64_t merged = 0;         // epochs whose merges were launched
+    int64_t merged_prev = 0;    // ... before this round's merges
     int64_t lo = 0;             // first sample of epoch k + 1
     bool spec = false;          // epoch k's sampler was queued speculatively
     bool done = false;
@@ -360,6 +369,8 @@ struct Query {
     std::chrono::steady_clock::time_point t_submit, t_done;
 
     int64_t bound(int64_t epoch) const { return std::min<int64_t>(epoch * N, omega); }
+    int32_t set_of(int64_t epoch) const { return (int32_t)(epoch % nsets); }
+    size_t frames_count() const { return (size_t)nsets * (size_t)nframes * (size_t)gd->n; }
     ~Query()
     {
         dev_free(counts);
@@ -573,19 +584,19 @@ int Runner::start_query(Query &q, int64_t *fc)
     q.status = KADABRA_OK;
     const size_t n = (size_t)q.gd->n;
     if (!q.counts) HIP_OR_FAIL(alloc_n(&q.counts, n, fc));
-    if (q.frames_len != 2 * (size_t)q.nframes * n) {
+    if (q.frames_len != q.frames_count()) {
         dev_release(q.frames);
         q.frames_len = 0;
-        HIP_OR_FAIL(alloc_n(&q.frames, 2 * (size_t)q.nframes * n, fc));
-        q.frames_len = 2 * (size_t)q.nframes * n;
+        HIP_OR_FAIL(alloc_n(&q.frames, q.frames_count(), fc));
+        q.frames_len = q.frames_count();
     }
     if (free_cslots.empty()) return fail(KADABRA_ESTATE, "no free control block");
     q.cslot = free_cslots.back();
     free_cslots.pop_back();
     HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)q.counts, n, 0u, stream));
-    HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)q.frames, 2 * (size_t)q.nframes * n, 0u, stream));
+    HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)q.frames, q.frames_count(), 0u, stream));
     HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)(d_ctl + q.cslot), sizeof(kd::Control) / 4, 0u, stream));
-    q.k = q.merged = q.lo = 0;
+    q.k = q.merged = q.merged_prev = q.lo = 0;
     q.spec = false;
     q.done = false;
     q.status = KADABRA_OK;
@@ -678,30 +689,36 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
         Launch L;
         for (size_t x = 0; x < qs.size(); ++x) {
             Query &q = *qs[x];
-            const int64_t epoch = q.k + 1;
-            int64_t hi = q.bound(epoch);
-            if (sample_cap >= 0) hi = std::min(hi, sample_cap);
+            // the next epl epochs (fewer where omega or the sample cap ends them);
+            // callers pass only queries with samples left
+            int64_t epoch = q.k, hi = q.lo;
+            for (int j = 0; j < q.epl && hi < q.omega && (sample_cap < 0 || hi < sample_cap); ++j) {
+                ++epoch;
+                hi = q.bound(epoch);
+                if (sample_cap >= 0) hi = std::min(hi, sample_cap);
+            }
             kd::QueryDesc &d = h[x];
             d.row_ptr = q.gd->d_row_ptr;
             d.col = q.gd->d_col;
             d.comp = q.gd->d_comp;
-            d.parity = (int32_t)(epoch & 1);
-            d.frames = q.frames + (size_t)d.parity * q.nframes * (size_t)q.gd->n;
+            d.frames = q.frames;
             d.ctl = d_ctl + q.cslot;
             d.seed = q.seed;
             d.lo = q.lo;
             d.hi = hi;
+            d.epoch_len = q.N;
             d.claim_begin = total;
             d.probe_min = q.probe_min;
             d.num_arcs = q.gd->arcs;
             d.n = q.gd->n;
             d.nframes = q.nframes;
-            d.gate = speculative ? (int32_t)(q.k & 1) : -1;
+            d.nsets = q.nsets;
+            d.gate = speculative ? q.set_of(q.k) : -1;
             total += hi - q.lo;
+            L.items.push_back({&q, q.k + 1});  // the launch's first epoch
             q.k = epoch;
             q.lo = hi;
             q.spec = speculative;
-            L.items.push_back({&q, epoch});
         }
         HIP_OR_FAIL(hipMemcpyAsync(d_qt[r], h, qs.size() * sizeof(kd::QueryDesc), hipMemcpyHostToDevice, stream));
         kd::SampleArgs sa{};
@@ -725,38 +742,52 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
         return KADABRA_OK;
     };
 
+    // Merges the launched epochs merged+1 .. k of every query in order: one
+    // merge-and-check launch per position, each boundary gated on the one
+    // before it (the first follows a boundary the host has seen continue).
     auto launch_merge = [&](std::vector<Query *> &qs) -> int {
         if (qs.empty()) return KADABRA_OK;
-        const int r = ring_pos;
-        ring_pos = (ring_pos + 1) % RING;
-        kd::MergeDesc *h = h_mt[r];
-        int32_t blocks = 0;
-        for (size_t x = 0; x < qs.size(); ++x) {
-            Query &q = *qs[x];
-            const int64_t epoch = q.k;  // its sampler has been launched
-            kd::MergeDesc &m = h[x];
-            m.counts = q.counts;
-            m.parity = (int32_t)(epoch & 1);
-            m.frames = q.frames + (size_t)m.parity * q.nframes * (size_t)q.gd->n;
-            m.ctl = d_ctl + q.cslot;
-            m.tau = q.lo;
-            m.omega = q.omega;
-            m.L = q.L;
-            m.eps = q.eps;
-            m.n = q.gd->n;
-            m.nframes = q.nframes;
-            m.gate = -1;  // the host knows the previous boundary continued
-            m.do_check = (sample_cap < 0 && q.lo < q.omega) ? 1 : 0;
-            m.block_begin = blocks;
-            blocks += kd::merge_blocks_for(q.gd->n);
-            q.merged = epoch;
+        int64_t depth = 0;
+        for (Query *q : qs) {
+            q->merged_prev = q->merged;
+            depth = std::max(depth, q->k - q->merged);
         }
-        HIP_OR_FAIL(hipMemcpyAsync(d_mt[r], h, qs.size() * sizeof(kd::MergeDesc), hipMemcpyHostToDevice, stream));
-        kd::MergeArgs ma{};
-        ma.m = d_mt[r];
-        ma.nq = (int32_t)qs.size();
-        ma.nblocks = blocks;
-        HIP_OR_FAIL(kd::launch_merge_check(ma, stream));
+        for (int64_t j = 1; j <= depth; ++j) {
+            const int r = ring_pos;
+            ring_pos = (ring_pos + 1) % RING;
+            kd::MergeDesc *h = h_mt[r];
+            int32_t blocks = 0, nq = 0;
+            for (Query *qp : qs) {
+                Query &q = *qp;
+                if (q.k - q.merged_prev < j) continue;
+                const int64_t epoch = q.merged_prev + j;
+                int64_t tau = q.bound(epoch);
+                if (sample_cap >= 0) tau = std::min(tau, sample_cap);
+                kd::MergeDesc &m = h[nq++];
+                m.counts = q.counts;
+                m.set = q.set_of(epoch);
+                m.frames = q.frames + (size_t)m.set * q.nframes * (size_t)q.gd->n;
+                m.ctl = d_ctl + q.cslot;
+                m.tau = tau;
+                m.omega = q.omega;
+                m.L = q.L;
+                m.eps = q.eps;
+                m.n = q.gd->n;
+                m.nframes = q.nframes;
+                m.gate = (j == 1) ? -1 : q.set_of(epoch - 1);
+                m.do_check = (sample_cap < 0 && tau < q.omega) ? 1 : 0;
+                m.block_begin = blocks;
+                blocks += kd::merge_blocks_for(q.gd->n);
+            }
+            HIP_OR_FAIL(hipMemcpyAsync(d_mt[r], h, (size_t)nq * sizeof(kd::MergeDesc), hipMemcpyHostToDevice,
+                                       stream));
+            kd::MergeArgs ma{};
+            ma.m = d_mt[r];
+            ma.nq = nq;
+            ma.nblocks = blocks;
+            HIP_OR_FAIL(kd::launch_merge_check(ma, stream));
+        }
+        for (Query *q : qs) q->merged = q->k;
         return KADABRA_OK;
     };
 
@@ -784,8 +815,6 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
         std::vector<Query *> still, finished;
         for (Query *q : active) {
             const kd::Control &c = h_ctl[q->cslot];
-            const int64_t tau = q->bound(q->merged);
-            const bool capped = sample_cap >= 0 && std::min(tau, sample_cap) >= sample_cap;
             int dec = 0;
             if (c.err) {
                 static const char *const site[] = {"?", "more BFS levels than the vertex-diameter bound",
@@ -797,15 +826,18 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
                                  (unsigned long long)q->seed, q->gd->n);
                 status = q->status;
                 pool_dirty = true;
-            } else if (capped) {
-                dec = 2;
-            } else if (tau == q->omega) {
-                dec = 2;
-            } else if (c.viol[q->merged & 1] == 0) {
-                dec = 1;
+                q->tau = q->bound(q->merged);
+            } else {
+                // this round's boundaries in order, up to the first that stops
+                for (int64_t e = q->merged_prev + 1; e <= q->merged && dec == 0; ++e) {
+                    int64_t tau = q->bound(e);
+                    if (sample_cap >= 0) tau = std::min(tau, sample_cap);
+                    if ((sample_cap >= 0 && tau >= sample_cap) || tau == q->omega) dec = 2;
+                    else if (c.viol[q->set_of(e)] == 0) dec = 1;
+                    q->tau = tau;
+                    q->decisions.push_back((int8_t)dec);
+                }
             }
-            q->tau = std::min(tau, sample_cap >= 0 ? sample_cap : tau);
-            q->decisions.push_back((int8_t)dec);
             if (dec || q->status != KADABRA_OK) {
                 q->decision = dec;
                 for (int w = 0; w < kd::ST_COUNT; ++w) q->work[w] = c.stats_total[w];
@@ -924,10 +956,11 @@ struct kadabra_server {
     std::thread worker;
 
     ~kadabra_server();
-    int64_t charge_of(const GraphData &g) const
+    int64_t frame_bytes_of(const GraphData &g) const
     {
-        return (int64_t)g.n * (4 + 8 + 8 * (int64_t)params.frames);
+        return (int64_t)g.n * 4 * 2 * params.epochs * (int64_t)params.frames;
     }
+    int64_t charge_of(const GraphData &g) const { return (int64_t)g.n * (4 + 8) + frame_bytes_of(g); }
     void *take_bin(size_t bytes)
     {
         auto it = bins.find(bytes);
@@ -963,7 +996,7 @@ struct kadabra_server {
             active += 1;
             peak_active = std::max(peak_active, active);
             v->counts = (int32_t *)take_bin(n * sizeof(int32_t));
-            const size_t fl = 2 * (size_t)v->nframes * n;
+            const size_t fl = v->frames_count();
             v->frames = (int32_t *)take_bin(fl * sizeof(int32_t));
             v->frames_len = v->frames ? fl : 0;
             v->scores = (double *)take_bin(n * sizeof(double));
@@ -996,6 +1029,8 @@ int make_query(Query &q, const GraphData &gd, const Params &p, double eps, doubl
     q.seed = seed;
     q.N = N;
     q.nframes = p.frames;
+    q.epl = p.epochs;
+    q.nsets = 2 * p.epochs;
     q.probe_min = p.probe_min;
     q.omega = omega;
     q.L = std::log(4.0 * (double)gd.n / delta);
@@ -1468,6 +1503,8 @@ int kadabra_batch_run(kadabra_batch *b)
     std::vector<Query *> qs;
     for (auto &q : b->queries) {
         q->nframes = b->params.frames;
+        q->epl = b->params.epochs;
+        q->nsets = 2 * b->params.epochs;
         q->probe_min = b->params.probe_min;
         qs.push_back(q.get());
     }
@@ -1602,7 +1639,7 @@ int kadabra_server_submit(kadabra_server *s, int32_t graph_index, double eps, do
     const GraphData &gd = *s->graphs[(size_t)graph_index];
     OK_OR_RETURN(make_query(*v, gd, s->params, eps, delta, seed, check_interval));
     v->charge = s->charge_of(gd);
-    v->frame_bytes = (int64_t)gd.n * 8 * (int64_t)s->params.frames;
+    v->frame_bytes = s->frame_bytes_of(gd);
     if (v->charge > s->budget)
         return fail(KADABRA_ERANGE, "query needs %lld device bytes, budget is %lld", (long long)v->charge,
                     (long long)s->budget);

@@ -23,14 +23,19 @@ enum StatIdx {
     ST_COUNT
 };
 
+// Epochs (check intervals) in flight per query are kept apart in frame sets:
+// epoch e (samples [B_{e-1}, B_e)) uses set e mod nsets, nsets = 2 x (epochs
+// per launch), so a launch and the speculative launch after it never share one.
+constexpr int kMaxSets = 8;
+
 // Device control block of one adaptive run (one per query).
 struct Control {
-    int32_t viol[2];                 // stopping-rule violations, by epoch parity
+    int32_t viol[kMaxSets];          // stopping-rule violations of a boundary, by epoch set
     int32_t err;                     // device-side invariant failure (0 = none), by site:
                                      // 1 level bound, 2 no predecessor, 3 frontier empty
     int32_t pad;
     int64_t err_sample;              // sample index of the first failure
-    int64_t stats[2][ST_COUNT];      // work counters of the epoch in flight, by parity
+    int64_t stats[kMaxSets][ST_COUNT];  // work counters of epochs in flight, by set
     int64_t stats_total[ST_COUNT];   // work counters of merged epochs
     int64_t phase_cycles[8];         // per-phase cycles (phase-timer builds only)
 };
@@ -50,23 +55,25 @@ struct SlotState {
     int32_t code_stride;  // words per slot (ceil(nstride / 8), rounded up to 64 bytes)
 };
 
-// One query's epoch in a sampling launch.
+// One query's consecutive epochs in a sampling launch.
 struct QueryDesc {
     const int32_t *row_ptr;
     const int32_t *col;
     const int32_t *comp;
-    int32_t *frames;      // this epoch's frame set: [nframes][n]
+    int32_t *frames;      // every frame set: [nsets][nframes][n]
     Control *ctl;
     uint64_t seed;
-    int64_t lo, hi;       // sample indices of this epoch: [lo, hi)
+    int64_t lo, hi;       // sample indices of this launch: [lo, hi), whole epochs (the last
+                          // one may end at omega)
+    int64_t epoch_len;    // N: sample i belongs to epoch i / N + 1
     int64_t claim_begin;  // launch-wide claim index of sample lo
     int64_t probe_min;    // >= 0: probe expansions of at least this many arcs; -1: auto rule
     int64_t num_arcs;
     int32_t n;
     int32_t nframes;
-    int32_t parity;       // epoch parity (frames, stats, flag)
-    int32_t gate;         // -1, or the parity of the previous boundary: if its check found
-                          // no violation the run has stopped and this epoch does no work
+    int32_t nsets;        // frame sets (epoch e uses set e mod nsets)
+    int32_t gate;         // -1, or the set of the boundary before lo: if its check found no
+                          // violation the run has stopped and this launch does no work for it
 };
 
 struct SampleArgs {
@@ -88,8 +95,8 @@ struct MergeDesc {
     double L, eps;
     int32_t n;
     int32_t nframes;
-    int32_t parity;
-    int32_t gate;         // as in QueryDesc: skip if the run stopped at the previous boundary
+    int32_t set;          // the epoch's set (flag and work counters)
+    int32_t gate;         // -1, or the set of the previous boundary: skip if the run stopped there
     int32_t do_check;     // 0: merge only (tau == omega)
     int32_t block_begin;  // first block of this query in the launch
 };

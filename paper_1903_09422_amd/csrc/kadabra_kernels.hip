@@ -1,8 +1,8 @@
 // kadabra_kernels.hip -- gfx950 kernels of the KADABRA adaptive-sampling path.
 //
-//   sample_kernel      one team (a wavefront of 64 lanes or a workgroup of 256)
-//                      per sample in flight; persistent over the epoch's sample
-//                      indices, claimed from a counter.  Per sample: pair draw,
+//   sample_kernel      one team (one to eight wavefronts) per sample in flight;
+//                      persistent over the sample indices of the launch (one or
+//                      more epochs of each query), claimed from a counter.  Per sample: pair draw,
 //                      same-component test, balanced bidirectional BFS with
 //                      128-bit path counts, meeting-vertex draw, backtracking
 //                      on CSR + distances, +1 on the interior vertices
@@ -475,10 +475,14 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
     int32_t *const loff0 = a.st.loff + (2 * slot) * (size_t)a.st.lcap;
     int32_t *const loff1 = loff0 + a.st.lcap;
 
-    // the flag this launch's boundaries will raise starts clear (it was last
-    // read two boundaries ago; this launch reads only the other parity)
+    // the flags of this launch's boundaries start clear (their sets were last
+    // read at least one launch ago; a launch reads only the set before lo)
     if (blockIdx.x == 0)
-        for (int32_t k = lane; k < a.nq; k += TEAM) a.q[k].ctl->viol[a.q[k].parity] = 0;
+        for (int32_t k = lane; k < a.nq; k += TEAM) {
+            const QueryDesc &d = a.q[k];
+            for (int64_t e = d.lo / d.epoch_len + 1; e <= (d.hi - 1) / d.epoch_len + 1; ++e)
+                d.ctl->viol[e % d.nsets] = 0;
+        }
 
 #ifdef KADABRA_PHASE_TIMERS
     uint64_t ph_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -520,11 +524,12 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
         // the query's fields, once, into scalar registers
         const QueryDesc *const qd = a.q + uniform_i32(sm.query);
         Control *const qctl = qd->ctl;
-        const int32_t qpar = qd->parity, qgate = qd->gate;
+        const int32_t qgate = qd->gate;
         // launched before the host has read the previous boundary's check:
         // stream order has already run that check, so its flag decides
         if (qgate >= 0 && qctl->viol[qgate] == 0) continue;
         const int64_t i = qd->lo + (jc - qd->claim_begin);
+        const int32_t qpar = (int32_t)((i / qd->epoch_len + 1) % qd->nsets);  // the epoch's set
         // graph arrays live in device global memory: say so, so that their
         // loads are global (not flat) instructions
         const gint32_t *const row_ptr = as_global(qd->row_ptr);
@@ -533,7 +538,8 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
         const int32_t nv = qd->n;
         const uint64_t seed = qd->seed;
         const int64_t probe_min = qd->probe_min, num_arcs = qd->num_arcs;
-        int32_t *const frame = qd->frames + (size_t)(blockIdx.x % qd->nframes) * (size_t)nv;
+        int32_t *const frame =
+            qd->frames + ((size_t)qpar * qd->nframes + (size_t)(blockIdx.x % qd->nframes)) * (size_t)nv;
         if (qctl != acc_ctl || qpar != acc_par) {
             flush();
             acc_ctl = qctl;
@@ -1102,11 +1108,11 @@ __global__ __launch_bounds__(MERGE_BLOCK) void merge_check_kernel(MergeArgs a)
             if (!(fv <= M.eps) || !(gv <= M.eps)) viol = 1;
         }
     }
-    if (__syncthreads_or(viol) && threadIdx.x == 0) atomicOr(&M.ctl->viol[M.parity], 1);
+    if (__syncthreads_or(viol) && threadIdx.x == 0) atomicOr(&M.ctl->viol[M.set], 1);
     if (qb == 0 && threadIdx.x < ST_COUNT) {
         // fold the epoch's work counters into the run's totals
-        M.ctl->stats_total[threadIdx.x] += M.ctl->stats[M.parity][threadIdx.x];
-        M.ctl->stats[M.parity][threadIdx.x] = 0;
+        M.ctl->stats_total[threadIdx.x] += M.ctl->stats[M.set][threadIdx.x];
+        M.ctl->stats[M.set][threadIdx.x] = 0;
     }
 }
 

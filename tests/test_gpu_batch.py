@@ -36,13 +36,14 @@ def _same(got, want):
         assert got.stats[k] == want.stats[k], k
 
 
-@pytest.mark.parametrize("team,overlap", [(256, 1), (128, 1), (64, 1), (256, 0)])
-def test_batch_mix_equals_oracle(team, overlap):
-    print(f"case batch mix team={team} overlap={overlap}", flush=True)
+@pytest.mark.parametrize("team,overlap,epl", [(256, 1, 2), (128, 1, 2), (64, 1, 1), (256, 0, 3), (256, 1, 4)])
+def test_batch_mix_equals_oracle(team, overlap, epl):
+    print(f"case batch mix team={team} overlap={overlap} epochs_per_launch={epl}", flush=True)
     handles = [Graph.from_csr(g) for g, *_ in MIX]
     with Batch() as b:
         b.set_param("team", team)
         b.set_param("overlap", overlap)
+        b.set_param("epochs_per_launch", epl)
         for h, (g, eps, seed, n_check) in zip(handles, MIX):
             b.add(h, eps, 0.1, seed, n_check)
         b.run()

@@ -66,11 +66,14 @@ def test_small_graphs(g, team, probe):
 
 @pytest.mark.parametrize("n_check", [1, 7, 1000, 10**6])
 def test_check_intervals_and_ragged_last_epoch(n_check):
+    """Every check interval, with one to four epochs per sampling launch (a run
+    may stop at any boundary inside a launch, and at omega mid-launch)."""
     g = G.erdos_renyi(400, 5.0, seed=8)
     print(f"case er400 n_check={n_check}", flush=True)
     want = oracle.run(g, 0.04, 0.1, 3, n_check)
-    got = gpu_run(g, 0.04, 0.1, 3, n_check)
-    assert_same(got, want)
+    for epl, overlap in ((2, 1), (1, 1), (3, 1), (4, 0), (4, 1)):
+        got = gpu_run(g, 0.04, 0.1, 3, n_check, epochs_per_launch=epl, overlap=overlap)
+        assert_same(got, want)
 
 
 def test_layered_graph_with_huge_sigma():
@@ -135,7 +138,8 @@ def test_mapping_does_not_change_results():
     print("case rmat18 mappings", flush=True)
     base = gpu_run(g, eps, delta, 5, n_check, team=256)
     for params in ({"team": 64}, {"team": 128}, {"team": 512}, {"team": 256, "slots": 37}, {"team": 64, "slots": 1000},
-                   {"team": 128, "slots": 2048},
+                   {"team": 128, "slots": 2048}, {"epochs_per_launch": 1}, {"epochs_per_launch": 3},
+                   {"epochs_per_launch": 4, "overlap": 0},
                    {"frames": 8}, {"overlap": 0}, {"team": 64, "frames": 3, "overlap": 0},
                    {"probe_min": 0}, {"probe_min": 1 << 40}, {"team": 64, "probe_min": 0}):
         print("  mapping", params, flush=True)

@@ -33,8 +33,9 @@ def _same(got, want):
         assert got.stats[k] == want.stats[k], k
 
 
-def _charge(n, frames=1):
-    return n * (4 + 8 + 8 * frames)
+def _charge(n, frames=1, epochs=2):
+    # counters 4n + scores 8n + one frame set per epoch in flight (2 per launched epoch)
+    return n * (4 + 8 + 8 * epochs * frames)
 
 
 def test_serve_staggered_equals_oracle():
