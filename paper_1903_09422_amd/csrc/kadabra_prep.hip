@@ -134,14 +134,31 @@ __global__ void cc_flatten_kernel(int32_t *parent, int32_t n)
     }
 }
 
-// key[c] = max over the component's vertices of (degree << 32 | (n - 1 - id))
+// key[c] = max over the component's vertices of (degree << 32 | (n - 1 - id)).
+// A wavefront whose vertices all lie in one component (the usual case: one
+// large component) takes the maximum by shuffles and makes one atomic.
 __global__ void root_key_kernel(const int32_t *row_ptr, const int32_t *comp, int32_t n,
                                 unsigned long long *key)
 {
-    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        const unsigned long long k = ((unsigned long long)(uint32_t)(row_ptr[v + 1] - row_ptr[v]) << 32) |
-                                     (unsigned long long)(uint32_t)(n - 1 - v);
-        atomicMax(&key[comp[v]], k);
+    const int32_t stride = gridDim.x * blockDim.x;
+    const int32_t start = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t span = (n + stride - 1) / stride * stride;  // same trip count for all lanes
+    for (int32_t v = start; v < span; v += stride) {
+        const bool in = v < n;
+        const int32_t c = in ? comp[v] : -1;
+        unsigned long long k = in ? (((unsigned long long)(uint32_t)(row_ptr[v + 1] - row_ptr[v]) << 32) |
+                                     (unsigned long long)(uint32_t)(n - 1 - v))
+                                  : 0ull;
+        const int32_t c0 = __shfl(c, 0, 64);
+        if (__all(!in || c == c0) && c0 >= 0) {
+            for (int o = 32; o > 0; o >>= 1) {
+                const unsigned long long x = __shfl_xor(k, o, 64);
+                k = x > k ? x : k;
+            }
+            if ((threadIdx.x & 63) == 0) atomicMax(&key[c0], k);
+        } else if (in) {
+            atomicMax(&key[c], k);
+        }
     }
 }
 
