@@ -213,10 +213,12 @@ def bench_batch(args) -> int:
     handles = [Graph.from_csr(g) for g, *_ in pool]
     for h, (g, eps, delta, n_check, seed) in zip(handles, pool):
         h.set_param("check_interval", n_check)
+        h.set_param("epochs_per_launch", args.epochs_per_launch)
     batch = Batch()
     batch.set_param("team", args.team)
     batch.set_param("slots", args.slots)
     batch.set_param("probe_min", args.probe_min)
+    batch.set_param("epochs_per_launch", args.epochs_per_launch)
     for h, (g, eps, delta, n_check, seed) in zip(handles, pool):
         batch.add(h, eps, delta, seed, n_check)
 
@@ -323,7 +325,8 @@ def bench_serve(args) -> int:
     legs = {}
     for name, max_active in (("one_at_a_time", 1), ("batching", 0)):
         srv = Server(handles, max_active=max_active)
-        for k, v in (("team", args.team), ("slots", args.slots), ("probe_min", args.probe_min)):
+        for k, v in (("team", args.team), ("slots", args.slots), ("probe_min", args.probe_min),
+                     ("epochs_per_launch", args.epochs_per_launch)):
             srv.set_param(k, v)
         replay(srv, None)  # warm-up: pool, buffers, code
         torch.cuda.synchronize()
