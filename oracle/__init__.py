@@ -30,7 +30,9 @@ def build(force: bool = True) -> str:
 class Stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "tau", "omega", "vd", "epochs", "v_exp", "e_scan", "v_new", "e_pred", "e_bt",
-        "path_interior", "disconnected", "rescaled_levels")] + [("L", C.c_double)]
+        "path_interior", "disconnected", "rescaled_levels")] + [("L", C.c_double)] + [
+        (k, C.c_int64) for k in ("first_samples", "plan_tau", "first_v_exp", "first_e_scan",
+                                 "first_e_bt", "first_path_interior", "first_disconnected")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -86,6 +88,22 @@ def lib():
         L.oracle_run.argtypes = [C.c_int32, i32p, i32p, C.c_double, C.c_double, C.c_uint64,
                                  C.c_int64, C.c_int64, i32p, C.POINTER(Stats),
                                  np.ctypeslib.ndpointer(np.int8, flags="C_CONTIGUOUS"), C.c_int64]
+        L.oracle_check_stop_v.argtypes = [C.c_int32, i32p, C.c_int64, C.c_int64, f64p, f64p,
+                                          C.c_double]
+        L.oracle_check_stop_v.restype = C.c_int
+        L.oracle_first_phase_samples.argtypes = [C.c_int64]
+        L.oracle_first_phase_samples.restype = C.c_int64
+        L.oracle_plan_lfg.argtypes = [C.c_double, C.c_int64, C.c_int64, C.c_double,
+                                      C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.oracle_plan_sum.argtypes = [C.c_int32, i32p, C.c_int64, C.c_int64, C.c_int64, C.c_double]
+        L.oracle_plan_sum.restype = C.c_double
+        L.oracle_plan.argtypes = [C.c_int32, i32p, C.c_int64, C.c_int64, C.c_double, C.c_double,
+                                  C.c_double, f64p, f64p]
+        L.oracle_plan.restype = C.c_int64
+        L.oracle_run_balanced.argtypes = [
+            C.c_int32, i32p, i32p, C.c_double, C.c_double, C.c_uint64, C.c_int64, C.c_int64,
+            C.c_int64, i32p, C.POINTER(Stats), np.ctypeslib.ndpointer(np.int8, flags="C_CONTIGUOUS"),
+            C.c_int64, f64p, f64p, i32p]
         L.oracle_sample.argtypes = [C.c_int32, i32p, i32p, i32p, C.c_uint64, C.c_uint64, i32p,
                                     C.POINTER(SampleInfo)]
         L.oracle_sample.restype = C.c_int32
@@ -164,12 +182,53 @@ def check_stop(counts, tau: int, omega_: int, L: float, eps: float) -> bool:
     return bool(lib().oracle_check_stop(c.size, c, tau, omega_, L, eps))
 
 
+def check_stop_v(counts, tau: int, omega_: int, LL, LU, eps: float) -> bool:
+    """The stopping rule with per-vertex log(1/delta_L(v)), log(1/delta_U(v))."""
+    c = np.ascontiguousarray(counts, dtype=np.int32)
+    LL = np.ascontiguousarray(LL, dtype=np.float64)
+    LU = np.ascontiguousarray(LU, dtype=np.float64)
+    return bool(lib().oracle_check_stop_v(c.size, c, tau, omega_, LL, LU, eps))
+
+
+# First-phase sample m is sample index FIRST_PHASE_BASE + m (a stream the
+# adaptive loop never reaches).
+FIRST_PHASE_BASE = 1 << 63
+
+
+def first_phase_samples(omega_: int) -> int:
+    return int(lib().oracle_first_phase_samples(omega_))
+
+
+def plan_lfg(b: float, t: int, omega_: int, eps: float) -> tuple:
+    """Largest log(1/delta_L), log(1/delta_U) with f, g <= eps at (b, t)."""
+    lf, lg = C.c_double(), C.c_double()
+    lib().oracle_plan_lfg(b, t, omega_, eps, C.byref(lf), C.byref(lg))
+    return lf.value, lg.value
+
+
+def plan_sum(c1, m1: int, t: int, omega_: int, eps: float) -> float:
+    c = np.ascontiguousarray(c1, dtype=np.int32)
+    return float(lib().oracle_plan_sum(c.size, c, m1, t, omega_, eps))
+
+
+def plan(c1, m1: int, omega_: int, eps: float, delta: float, L: float) -> tuple:
+    """(t*, LL, LU) of the balancing rule; t* = 0: no plan, uniform L."""
+    c = np.ascontiguousarray(c1, dtype=np.int32)
+    LL = np.zeros(c.size)
+    LU = np.zeros(c.size)
+    t = lib().oracle_plan(c.size, c, m1, omega_, eps, delta, L, LL, LU)
+    return int(t), LL, LU
+
+
 @dataclass
 class RunResult:
     tau: int
     counts: np.ndarray
     stats: dict
     decisions: np.ndarray  # per boundary: 0 = continue, 1 = stop rule met, 2 = omega reached
+    LL: np.ndarray = None  # balanced runs: log(1/delta_L(v)), log(1/delta_U(v)), first-phase counts
+    LU: np.ndarray = None
+    c1: np.ndarray = None
 
     @property
     def scores(self) -> np.ndarray:
@@ -177,17 +236,24 @@ class RunResult:
 
 
 def run(g, eps: float, delta: float, seed: int, check_interval: int,
-        sample_cap: int = -1) -> RunResult:
+        sample_cap: int = -1, first_samples: int = 0) -> RunResult:
+    """The adaptive loop.  first_samples: 0 = uniform constants; -1 = balanced
+    with the default first phase; > 0 = balanced with that many samples."""
     n, rp, col = _csr(g)
     counts = np.zeros(n, dtype=np.int32)
     st = Stats()
     dec = np.full(1 << 16, -1, dtype=np.int8)
-    rc = lib().oracle_run(n, rp, col, eps, delta, seed, check_interval, sample_cap, counts,
-                          C.byref(st), dec, dec.size)
+    LL, LU = np.zeros(n), np.zeros(n)
+    c1 = np.zeros(n, dtype=np.int32)
+    rc = lib().oracle_run_balanced(n, rp, col, eps, delta, seed, check_interval, sample_cap,
+                                   first_samples, counts, C.byref(st), dec, dec.size, LL, LU, c1)
     if rc != 0:
         raise ValueError(f"oracle_run failed ({rc})")
     ne = min(int(st.epochs), dec.size)
-    return RunResult(tau=int(st.tau), counts=counts, stats=st.as_dict(), decisions=dec[:ne].copy())
+    r = RunResult(tau=int(st.tau), counts=counts, stats=st.as_dict(), decisions=dec[:ne].copy())
+    if first_samples != 0:
+        r.LL, r.LU, r.c1 = LL, LU, c1
+    return r
 
 
 def sample(g, comp, seed: int, i: int):

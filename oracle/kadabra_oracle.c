@@ -21,10 +21,14 @@
  *     distance vector (Appendix C.1);
  *   - per-sample reseeding by a sample index, which makes the result
  *     independent of the schedule (indexed-frame algorithm, Appendix D).
+ *   - optionally, per-vertex delta_L(v), delta_U(v) chosen from a first,
+ *     separate sampling phase (Section 2.3 requires only that their sum over
+ *     all vertices stays within delta; KADABRA's own balancing is in the
+ *     paper it cites, so the rule used here is a reading, derived below).
  * Readings of points on which the paper is silent (the balanced bidirectional
- * BFS rule, the omega formula, uniform delta_L/delta_U, the block-float sigma
- * representation, the random-draw assignment) are listed with the function
- * that takes them.
+ * BFS rule, the omega formula, uniform delta_L/delta_U, the balancing rule,
+ * the block-float sigma representation, the random-draw assignment) are
+ * listed with the function that takes them.
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared (no fast-math: the
  * stop test must evaluate the exact IEEE expression tree given below).
@@ -263,6 +267,121 @@ int oracle_check_stop(int32_t n, const int32_t *counts, int64_t tau, int64_t ome
         if (!(f <= eps) || !(g <= eps)) return 0;
     }
     return 1;
+}
+
+/* Same rule with separate constants: f uses log(1/delta_L(v)), g uses
+ * log(1/delta_U(v)) (the two invariants of Section 2.3). */
+int oracle_check_stop_v(int32_t n, const int32_t *counts, int64_t tau, int64_t omega,
+                        const double *LL, const double *LU, double eps)
+{
+    for (int32_t v = 0; v < n; ++v) {
+        double f, g, unused;
+        oracle_fg(counts[v], tau, omega, LL[v], &f, &unused);
+        oracle_fg(counts[v], tau, omega, LU[v], &unused, &g);
+        if (!(f <= eps) || !(g <= eps)) return 0;
+    }
+    return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Balancing delta_L(v), delta_U(v) (the adjacent step before the adaptive   */
+/* loop).  Section 2.3 fixes only sum_v delta_L(v) + delta_U(v) <= delta;    */
+/* this code spends delta/2 on it (as the uniform reading does) and keeps    */
+/* the other delta/2 for the omega cap.  Reading, derived from Appendix B:   */
+/*                                                                           */
+/*  1. A first phase draws M1 samples from a stream the adaptive loop never  */
+/*     uses: first-phase sample m is sample index 2^63 + m.  c1(v) counts    */
+/*     the first-phase paths through v; these samples are not part of the    */
+/*     estimate, so the constants do not depend on the adaptive samples.     */
+/*  2. Planning value b_p(v) = (c1(v) + 1) / M1 (add-one, so that a vertex   */
+/*     no first-phase path crossed still gets a positive value).            */
+/*  3. For a target sample count t, the largest L for which f(b_p, L, w, t)  */
+/*     <= eps has a closed form.  With x = L / t, af = 1/3 - w/t and         */
+/*     q = 2 b w / t, f = x af + sqrt(x^2 af^2 + q x) is increasing in x,   */
+/*     and f = eps at x = eps^2 / (q + 2 eps af).  If q + 2 eps af <= 0,     */
+/*     f stays below eps for every L (its limit is b w / (w - t/3)): then    */
+/*     L_f = +inf.  For g the same with ag = 1/3 + w/t (always finite).      */
+/*  4. S(t) = sum_v exp(-L_f(v, t)) + exp(-L_g(v, t)) is the failure budget  */
+/*     that makes every vertex meet the rule at t if b~ = b_p.  t* is found  */
+/*     by bisection on [1, omega] for S(t) <= (1 - beta) delta/2; if the     */
+/*     bisection ends at omega there is no plan and the uniform constants    */
+/*     are kept.                                                             */
+/*  5. delta_L(v) = (1 - beta) exp(-L_f(v, t*)) + beta delta / (4 n), and    */
+/*     delta_U(v) likewise: a floor share beta = 1/10 of the budget, spread  */
+/*     uniformly, covers vertices whose count grows past the plan.  Then    */
+/*     sum_v delta_L + delta_U = (1 - beta) S(t*) + beta delta/2 <= delta/2. */
+/*     The target carries a relative margin of 1e-6 for the rounding of S.  */
+/* Evaluated in IEEE double in exactly the order written, no contraction.    */
+/* ------------------------------------------------------------------------ */
+
+#define BALANCE_FLOOR 0.1
+#define FIRST_PHASE_BASE ((uint64_t)1 << 63)
+
+/* First-phase sample count when none is given: ceil(omega / 20). */
+int64_t oracle_first_phase_samples(int64_t omega)
+{
+    return (omega + 19) / 20;
+}
+
+/* L_f and L_g (step 3) for planning value b at target t. */
+void oracle_plan_lfg(double b, int64_t t_, int64_t omega, double eps, double *Lf, double *Lg)
+{
+    double t = (double)t_;
+    double w = (double)omega;
+    double af = 1.0 / 3.0 - w / t;
+    double ag = 1.0 / 3.0 + w / t;
+    double q = 2.0 * b * w / t;
+    double df = q + 2.0 * eps * af;
+    double dg = q + 2.0 * eps * ag;
+    double e2 = eps * eps;
+    *Lf = (df > 0.0) ? t * e2 / df : INFINITY;
+    *Lg = t * e2 / dg;
+}
+
+static double plan_b(int32_t c1, int64_t m1)
+{
+    return ((double)c1 + 1.0) / (double)m1;
+}
+
+/* S(t) of step 4, summed over the vertices in increasing id order. */
+double oracle_plan_sum(int32_t n, const int32_t *c1, int64_t m1, int64_t t, int64_t omega,
+                       double eps)
+{
+    double S = 0.0;
+    for (int32_t v = 0; v < n; ++v) {
+        double Lf, Lg;
+        oracle_plan_lfg(plan_b(c1[v], m1), t, omega, eps, &Lf, &Lg);
+        S += exp(-Lf);
+        S += exp(-Lg);
+    }
+    return S;
+}
+
+/* Steps 4-5: writes log(1/delta_L(v)), log(1/delta_U(v)) and returns t*
+ * (0: no plan, LL = LU = L, the uniform constant). */
+int64_t oracle_plan(int32_t n, const int32_t *c1, int64_t m1, int64_t omega, double eps,
+                    double delta, double L, double *LL, double *LU)
+{
+    double beta = BALANCE_FLOOR;
+    double target = (1.0 - beta) * (delta / 2.0) * (1.0 - 1e-6);
+    int64_t lo = 1, hi = omega;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (oracle_plan_sum(n, c1, m1, mid, omega, eps) <= target) hi = mid;
+        else lo = mid + 1;
+    }
+    if (lo >= omega) {
+        for (int32_t v = 0; v < n; ++v) LL[v] = LU[v] = L;
+        return 0;
+    }
+    double floor_share = beta * delta / (4.0 * (double)n);
+    for (int32_t v = 0; v < n; ++v) {
+        double Lf, Lg;
+        oracle_plan_lfg(plan_b(c1[v], m1), lo, omega, eps, &Lf, &Lg);
+        LL[v] = -log((1.0 - beta) * exp(-Lf) + floor_share);
+        LU[v] = -log((1.0 - beta) * exp(-Lg) + floor_share);
+    }
+    return lo;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -591,25 +710,69 @@ int oracle_setup(int32_t n, const int32_t *row_ptr, const int32_t *col, double e
     return 0;
 }
 
-int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, double eps, double delta,
-               uint64_t seed, int64_t check_interval, int64_t sample_cap, int32_t *counts,
-               oracle_stats *st, int8_t *decisions, int64_t max_decisions)
+/* First phase (balancing step 1): c1(v) over first-phase samples 0 .. m1-1,
+ * i.e. sample indices 2^63 .. 2^63 + m1 - 1.  Work counters go to st. */
+static int first_phase(struct sampler *S, int32_t n, uint64_t seed, int64_t m1, int32_t *c1,
+                       int32_t *interior, oracle_stats *st)
 {
-    if (check_interval < 1) return -1;
+    for (int32_t v = 0; v < n; ++v) c1[v] = 0;
+    for (int64_t m = 0; m < m1; ++m) {
+        int32_t ni = sample_path(S, seed, FIRST_PHASE_BASE + (uint64_t)m, interior, NULL, st);
+        if (ni < 0) { st->disconnected += 1; continue; }
+        for (int32_t q = 0; q < ni; ++q) c1[interior[q]] += 1;
+    }
+    return 0;
+}
+
+/* The adaptive loop.  first_samples: 0 = uniform delta_L = delta_U (no first
+ * phase); -1 = balanced with ceil(omega / 20) first-phase samples; > 0 =
+ * balanced with that many.  LL, LU (optional, n each) receive the constants
+ * used; c1 (optional, n) the first-phase counts. */
+int oracle_run_balanced(int32_t n, const int32_t *row_ptr, const int32_t *col, double eps,
+                        double delta, uint64_t seed, int64_t check_interval, int64_t sample_cap,
+                        int64_t first_samples, int32_t *counts, oracle_stats *st,
+                        int8_t *decisions, int64_t max_decisions, double *LL_out,
+                        double *LU_out, int32_t *c1_out)
+{
+    if (check_interval < 1 || first_samples < -1) return -1;
     memset(st, 0, sizeof(*st));
     int32_t *comp = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     int32_t *interior = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
-    if (!comp || !interior) return -2;
+    double *LL = (double *)malloc(sizeof(double) * (size_t)n);
+    double *LU = (double *)malloc(sizeof(double) * (size_t)n);
+    int32_t *c1 = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!comp || !interior || !LL || !LU || !c1) {
+        free(comp); free(interior); free(LL); free(LU); free(c1);
+        return -2;
+    }
     int32_t vd;
     int64_t omega;
     double L;
     if (oracle_setup(n, row_ptr, col, eps, delta, comp, &vd, &omega, &L) != 0) {
-        free(comp); free(interior);
+        free(comp); free(interior); free(LL); free(LU); free(c1);
         return -1;
     }
     st->vd = vd; st->omega = omega; st->L = L;
     struct sampler S;
-    if (sampler_init(&S, n, row_ptr, col, comp) != 0) return -2;
+    if (sampler_init(&S, n, row_ptr, col, comp) != 0) {
+        free(comp); free(interior); free(LL); free(LU); free(c1);
+        return -2;
+    }
+
+    for (int32_t v = 0; v < n; ++v) { LL[v] = LU[v] = L; c1[v] = 0; }
+    if (first_samples != 0) {
+        int64_t m1 = first_samples > 0 ? first_samples : oracle_first_phase_samples(omega);
+        oracle_stats fs;
+        memset(&fs, 0, sizeof(fs));
+        first_phase(&S, n, seed, m1, c1, interior, &fs);
+        st->first_samples = m1;
+        st->first_v_exp = fs.v_exp;
+        st->first_e_scan = fs.e_scan;
+        st->first_e_bt = fs.e_bt;
+        st->first_path_interior = fs.path_interior;
+        st->first_disconnected = fs.disconnected;
+        st->plan_tau = oracle_plan(n, c1, m1, omega, eps, delta, L, LL, LU);
+    }
     for (int32_t v = 0; v < n; ++v) counts[v] = 0;
 
     int64_t tau = 0, k = 0;
@@ -630,14 +793,25 @@ int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, double eps
             if (decisions && k - 1 < max_decisions) decisions[k - 1] = 2;
             break;
         }
-        int stop = oracle_check_stop(n, counts, tau, omega, L, eps);
+        int stop = oracle_check_stop_v(n, counts, tau, omega, LL, LU, eps);
         if (decisions && k - 1 < max_decisions) decisions[k - 1] = (int8_t)stop;
         if (stop) break;
     }
     st->tau = tau;
+    if (LL_out) memcpy(LL_out, LL, sizeof(double) * (size_t)n);
+    if (LU_out) memcpy(LU_out, LU, sizeof(double) * (size_t)n);
+    if (c1_out) memcpy(c1_out, c1, sizeof(int32_t) * (size_t)n);
     sampler_free(&S);
-    free(comp); free(interior);
+    free(comp); free(interior); free(LL); free(LU); free(c1);
     return 0;
+}
+
+int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, double eps, double delta,
+               uint64_t seed, int64_t check_interval, int64_t sample_cap, int32_t *counts,
+               oracle_stats *st, int8_t *decisions, int64_t max_decisions)
+{
+    return oracle_run_balanced(n, row_ptr, col, eps, delta, seed, check_interval, sample_cap, 0,
+                               counts, st, decisions, max_decisions, NULL, NULL, NULL);
 }
 
 /* Single sample, for the path-law and unbiasedness tests.  Returns the number

@@ -20,7 +20,14 @@ typedef struct {
     int64_t path_interior; /* counter increments */
     int64_t disconnected;  /* samples whose endpoints lie in different components */
     int64_t rescaled_levels; /* BFS levels whose sigma had to be divided by 2^sh */
-    double L;              /* log(1 / delta_L) */
+    double L;              /* log(1 / delta_L) (uniform) */
+    int64_t first_samples; /* balancing: first-phase samples (0 = uniform constants) */
+    int64_t plan_tau;      /* balancing: planned sample count t* (0 = no plan) */
+    int64_t first_v_exp;   /* work counters of the first phase */
+    int64_t first_e_scan;
+    int64_t first_e_bt;
+    int64_t first_path_interior;
+    int64_t first_disconnected;
 } oracle_stats;
 
 typedef struct {
@@ -47,6 +54,19 @@ double oracle_log_inv_delta(int32_t n, double delta);
 void oracle_fg(int32_t c, int64_t tau, int64_t omega, double L, double *f, double *g);
 int oracle_check_stop(int32_t n, const int32_t *counts, int64_t tau, int64_t omega, double L,
                       double eps);
+int oracle_check_stop_v(int32_t n, const int32_t *counts, int64_t tau, int64_t omega,
+                        const double *LL, const double *LU, double eps);
+int64_t oracle_first_phase_samples(int64_t omega);
+void oracle_plan_lfg(double b, int64_t t, int64_t omega, double eps, double *Lf, double *Lg);
+double oracle_plan_sum(int32_t n, const int32_t *c1, int64_t m1, int64_t t, int64_t omega,
+                       double eps);
+int64_t oracle_plan(int32_t n, const int32_t *c1, int64_t m1, int64_t omega, double eps,
+                    double delta, double L, double *LL, double *LU);
+int oracle_run_balanced(int32_t n, const int32_t *row_ptr, const int32_t *col, double eps,
+                        double delta, uint64_t seed, int64_t check_interval, int64_t sample_cap,
+                        int64_t first_samples, int32_t *counts, oracle_stats *st,
+                        int8_t *decisions, int64_t max_decisions, double *LL, double *LU,
+                        int32_t *c1);
 int oracle_setup(int32_t n, const int32_t *row_ptr, const int32_t *col, double eps, double delta,
                  int32_t *comp, int32_t *vd, int64_t *omega, double *L);
 int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, double eps, double delta,
