@@ -62,6 +62,14 @@ typedef struct {
     double ms_sample_kernels; /* summed HIP-event durations of the sampling launches whose
                                  samples count (epochs 1 .. epochs) */
     int64_t sample_launches;  /* number of those launches (= epochs) */
+    /* balanced runs ("balance" = 1); all zero otherwise */
+    int64_t first_samples; /* first-phase samples drawn (not part of tau or the counters) */
+    int64_t plan_tau;      /* planned sample count t* of the constants (0: no plan, uniform L) */
+    int64_t first_v_exp;   /* work counters of the first phase, as above */
+    int64_t first_e_scan;
+    int64_t first_e_bt;
+    int64_t first_path_interior;
+    int64_t first_disconnected;
 } kadabra_stats;
 
 /*
@@ -84,10 +92,12 @@ int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr,
 /*
  * Sets a run parameter; it applies to the next kadabra_run.
  *   "check_interval"  N >= 1: the stopping rule is checked after every N
- *                     samples (Appendix C.2).  Default 1024.  The only key
- *                     that changes results.
- *   "team"            0 (auto), 64 (one wavefront per sample), 128 (two)
- *                     or 256 (four wavefronts per sample).  Default 0.
+ *                     samples (Appendix C.2).  Default 1024.  With
+ *                     "balance" and "balance_samples", the only keys that
+ *                     change results.
+ *   "team"            0 (auto), 64 (one wavefront per sample), 128, 256 or
+ *                     512 (two, four or eight wavefronts per sample).
+ *                     Default 0.
  *   "slots"           samples in flight, 0 = auto (bounded by device memory).
  *   "frames"          counter frames F >= 1 the workgroups' increments are
  *                     spread over, merged at every boundary.  Default 1.
@@ -97,7 +107,18 @@ int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr,
  *                     check intervals; each boundary is still merged and
  *                     checked on exactly its own samples (the samples of later
  *                     intervals of a run that stops are discarded).  Default 2.
- *                     Default 1.
+ *   "balance"         1: per-vertex delta_L(v), delta_U(v) (Section 2.3 bounds
+ *                     only their sum) chosen from a first sampling phase, so
+ *                     that vertices whose counters need more samples get a
+ *                     larger share; 0 (default): uniform delta / (4 n).  The
+ *                     first phase draws sample indices 2^63 + m, m < M1, none
+ *                     of which the adaptive loop draws; its counts c1 give
+ *                     planning values (c1 + 1) / M1, f and g of Appendix B
+ *                     are inverted at a planned sample count t*, the smallest
+ *                     (by bisection) at which the summed probabilities fit in
+ *                     0.9 delta/2, and 0.1 delta/2 is spread evenly on top;
+ *                     if none fits below omega the uniform constants stay.
+ *   "balance_samples" M1 >= 1 first-phase samples; 0 (default): ceil(omega/20).
  *   "probe_min"       k >= 0: expansions scanning at least k arcs first look
  *                     for the meeting set without materialising the new level;
  *                     -1 (default): when the product of the two frontiers'
@@ -126,8 +147,9 @@ int kadabra_set_stream(kadabra_graph *g, void *hip_stream);
  * Runs adaptive sampling to completion (blocking): 0 < eps < 1 additive
  * error, 0 < delta < 1 failure probability, seed of the counter-based
  * generator.  omega = ceil(0.5/eps^2 (floor(log2(VD - 2)) + 1 + ln(2/delta)))
- * and uniform delta_L = delta_U = delta/(4n) (the paper defers both to the
- * original KADABRA analysis).  Samples are drawn in epochs [B_{k-1}, B_k),
+ * and uniform delta_L = delta_U = delta/(4n), or balanced per-vertex
+ * constants with "balance" (the paper defers both to the original KADABRA
+ * analysis).  Samples are drawn in epochs [B_{k-1}, B_k),
  * B_k = min(k N, omega); the stopping rule runs on the counters of exactly
  * samples [0, B_k).  A failed or canceled run leaves the handle usable and no
  * result readable.  Errors: EINVAL (eps, delta), ERANGE (omega >= 2^31),
@@ -157,6 +179,17 @@ int kadabra_get_scores_device(const kadabra_graph *g, double *scores_dev, int32_
  * receives the number of boundaries.  Errors: ESTATE.
  */
 int kadabra_get_decisions(const kadabra_graph *g, int8_t *out, int64_t cap, int64_t *count);
+
+/*
+ * The per-vertex constants of the last completed run, into caller-allocated
+ * host memory (any pointer may be NULL): log_inv_delta_L[v] =
+ * log(1/delta_L(v)) and log_inv_delta_U[v] = log(1/delta_U(v)) (double[n]),
+ * first_counts[v] = c1(v), the first-phase counter (int32[n]).  A run without
+ * "balance" reads L = log(4 n / delta) and zero counts.  Errors: ESTATE (no
+ * completed run), EDEVICE.
+ */
+int kadabra_get_balance(const kadabra_graph *g, double *log_inv_delta_L, double *log_inv_delta_U,
+                        int32_t *first_counts);
 
 /*
  * Evaluates the stopping-rule functions of Appendix B on the device for

@@ -92,6 +92,15 @@ class Graph:
         return RunResult(tau=int(st.tau), counts=counts, scores=scores, stats=st.as_dict(),
                          decisions=dec[: int(cnt.value)].copy())
 
+    def balance(self) -> tuple:
+        """The last run's per-vertex constants: (log(1/delta_L), log(1/delta_U),
+        first-phase counters); uniform L and zeros without "balance"."""
+        LL = np.empty(self.n, dtype=np.float64)
+        LU = np.empty(self.n, dtype=np.float64)
+        c1 = np.empty(self.n, dtype=np.int32)
+        check(lib().kadabra_get_balance(self._h, LL.ctypes.data, LU.ctypes.data, c1.ctypes.data))
+        return LL, LU, c1
+
     def autotune(self, eps: float, delta: float, trial_samples: int = 8192) -> dict:
         """Pick the fastest mapping (team, slots, probe) on a trial prefix;
         results never depend on it.  Returns the chosen parameters."""

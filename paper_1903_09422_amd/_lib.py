@@ -19,7 +19,7 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE"
 EXPORTS = (
     "kadabra_create_graph", "kadabra_set_param", "kadabra_get_param", "kadabra_set_stream",
     "kadabra_run", "kadabra_get_scores", "kadabra_get_scores_device", "kadabra_get_decisions",
-    "kadabra_eval_stop_fg", "kadabra_cancel", "kadabra_destroy_graph", "kadabra_last_error",
+    "kadabra_get_balance", "kadabra_eval_stop_fg", "kadabra_cancel", "kadabra_destroy_graph", "kadabra_last_error",
     "kadabra_version", "kadabra_autotune", "kadabra_batch_create", "kadabra_batch_set_param",
     "kadabra_batch_get_param", "kadabra_batch_set_stream", "kadabra_batch_add", "kadabra_batch_run",
     "kadabra_batch_autotune", "kadabra_batch_get_scores", "kadabra_batch_clear",
@@ -43,7 +43,9 @@ class Stats(C.Structure):
         "tau", "omega", "vd_bound", "epochs", "decision", "v_exp", "e_scan", "e_bt",
         "path_interior", "disconnected")] + [
         ("log_inv_delta", C.c_double), ("ms_sampling", C.c_double), ("ms_total", C.c_double),
-        ("ms_sample_kernels", C.c_double), ("sample_launches", C.c_int64)]
+        ("ms_sample_kernels", C.c_double), ("sample_launches", C.c_int64)] + [
+        (k, C.c_int64) for k in ("first_samples", "plan_tau", "first_v_exp", "first_e_scan",
+                                 "first_e_bt", "first_path_interior", "first_disconnected")]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -88,6 +90,7 @@ def lib() -> C.CDLL:
     L.kadabra_get_scores.argtypes = [vp, vp, vp, C.POINTER(Stats)]
     L.kadabra_get_scores_device.argtypes = [vp, vp, vp]
     L.kadabra_get_decisions.argtypes = [vp, vp, C.c_int64, i64p]
+    L.kadabra_get_balance.argtypes = [vp, vp, vp, vp]
     L.kadabra_eval_stop_fg.argtypes = [C.c_int32, vp, C.c_int64, C.c_int64, C.c_double, vp, vp]
     L.kadabra_cancel.argtypes = [vp]
     L.kadabra_destroy_graph.argtypes = [vp]

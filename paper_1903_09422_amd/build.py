@@ -9,6 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkadabra.so")
 SOURCES = [os.path.join(CSRC, "kadabra_kernels.hip"), os.path.join(CSRC, "kadabra_prep.hip"),
+           os.path.join(CSRC, "kadabra_balance.hip"),
            os.path.join(CSRC, "kadabra_host.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -75,6 +75,7 @@ int fail(int code, const char *fmt, ...)
 
 constexpr int32_t kMaxN = 1 << 23;       // n and every degree stay below 2^23
 constexpr int64_t kMaxOmega = INT32_MAX; // int32 counters
+constexpr int64_t kMaxFirstPhase = INT32_MAX - 1;  // int32 first-phase counters, m1 + 1 table rows
 
 // Device allocation.  *fail_countdown is a test hook: when it is positive it
 // counts allocations down and the one that brings it to zero fails with
@@ -187,6 +188,8 @@ struct Params {
     int overlap = 1;
     int epochs = 2;          // epochs (check intervals) per sampling launch, 1..4
     int64_t probe_min = -1;  // -1 auto rule
+    int balance = 0;         // 1: per-vertex delta_L, delta_U from a first sampling phase
+    int64_t balance_samples = 0;  // first-phase samples; 0: ceil(omega / 20)
     int64_t fail_alloc = 0;  // test hook
     int32_t level_cap = 0;   // test hook: 0, or a smaller level capacity per side
 };
@@ -217,6 +220,13 @@ int set_common_param(Params &p, const char *key, int64_t value, bool *known)
     } else if (!strcmp(key, "probe_min")) {
         if (value < -1) return fail(KADABRA_EINVAL, "probe_min must be >= -1");
         p.probe_min = value;
+    } else if (!strcmp(key, "balance")) {
+        if (value != 0 && value != 1) return fail(KADABRA_EINVAL, "balance must be 0 or 1");
+        p.balance = (int)value;
+    } else if (!strcmp(key, "balance_samples")) {
+        if (value < 0 || value > kMaxFirstPhase)
+            return fail(KADABRA_EINVAL, "balance_samples must be in [0, %lld]", (long long)kMaxFirstPhase);
+        p.balance_samples = value;
     } else if (!strcmp(key, "test_fail_alloc")) {
         if (value < 0) return fail(KADABRA_EINVAL, "test_fail_alloc must be >= 0");
         p.fail_alloc = value;
@@ -239,6 +249,8 @@ int get_common_param(const Params &p, const char *key, int64_t *value)
     else if (!strcmp(key, "overlap")) *value = p.overlap;
     else if (!strcmp(key, "epochs_per_launch")) *value = p.epochs;
     else if (!strcmp(key, "probe_min")) *value = p.probe_min;
+    else if (!strcmp(key, "balance")) *value = p.balance;
+    else if (!strcmp(key, "balance_samples")) *value = p.balance_samples;
     else if (!strcmp(key, "test_level_cap")) *value = p.level_cap;
     else return 1;
     return 0;
@@ -346,11 +358,15 @@ struct Query {
     int64_t probe_min = -1;
     int64_t omega = 0;
     double L = 0;
+    int64_t m1 = 0;             // balanced runs: first-phase samples (0: L for every vertex)
     // device buffers
     int32_t *counts = nullptr;
     int32_t *frames = nullptr;  // [nsets][nframes][n]
     size_t frames_len = 0;
     double *scores = nullptr;
+    int32_t *c1 = nullptr;      // balanced runs: first-phase counters [n]
+    void *plan_buf = nullptr;   // balanced runs: lcon [2 (m1 + 1)] doubles, then hist [m1 + 1]
+    size_t plan_len = 0;        // bytes of plan_buf
     int cslot = -1;             // control block index in the runner
     // progress
     int64_t k = 0;              // epochs whose samplers were launched
@@ -358,12 +374,15 @@ struct Query {
     int64_t merged_prev = 0;    // ... before this round's merges
     int64_t lo = 0;             // first sample of epoch k + 1
     bool spec = false;          // epoch k's sampler was queued speculatively
+    bool first_launched = false;  // the first phase and its plan are queued
     bool done = false;
     int status = KADABRA_OK;
     std::vector<int8_t> decisions;
     int64_t tau = 0;
     int decision = 0;
     int64_t work[kd::ST_COUNT] = {};
+    int64_t work_first[kd::ST_COUNT] = {};  // the first phase's work counters
+    int64_t plan_tau = 0;       // planned sample count t* (0: no plan)
     double ms_kernels = 0.0;    // sampler launches that did this query's work
     int64_t launches = 0;
     std::chrono::steady_clock::time_point t_submit, t_done;
@@ -371,11 +390,16 @@ struct Query {
     int64_t bound(int64_t epoch) const { return std::min<int64_t>(epoch * N, omega); }
     int32_t set_of(int64_t epoch) const { return (int32_t)(epoch % nsets); }
     size_t frames_count() const { return (size_t)nsets * (size_t)nframes * (size_t)gd->n; }
+    size_t plan_bytes() const { return m1 ? (size_t)(m1 + 1) * (2 * sizeof(double) + sizeof(int32_t)) : 0; }
+    double *lcon() const { return (double *)plan_buf; }
+    int32_t *hist() const { return (int32_t *)((char *)plan_buf + (size_t)(m1 + 1) * 2 * sizeof(double)); }
     ~Query()
     {
         dev_free(counts);
         dev_free(frames);
         dev_free(scores);
+        dev_free(c1);
+        dev_free(plan_buf);
     }
 };
 
@@ -504,9 +528,11 @@ struct Runner {
             if (h_mt[r]) (void)hipHostFree(h_mt[r]);
             h_qt[r] = nullptr;
             h_mt[r] = nullptr;
-            HIP_OR_FAIL(alloc_n(&d_qt[r], (size_t)ncap, fc));
+            // a query's first phase takes a second sampling descriptor
+            HIP_OR_FAIL(alloc_n(&d_qt[r], 2 * (size_t)ncap, fc));
             HIP_OR_FAIL(alloc_n(&d_mt[r], (size_t)ncap, fc));
-            HIP_OR_FAIL(hipHostMalloc((void **)&h_qt[r], (size_t)ncap * sizeof(kd::QueryDesc), hipHostMallocDefault));
+            HIP_OR_FAIL(hipHostMalloc((void **)&h_qt[r], 2 * (size_t)ncap * sizeof(kd::QueryDesc),
+                                      hipHostMallocDefault));
             HIP_OR_FAIL(hipHostMalloc((void **)&h_mt[r], (size_t)ncap * sizeof(kd::MergeDesc), hipHostMallocDefault));
         }
         table_cap = ncap;
@@ -590,6 +616,17 @@ int Runner::start_query(Query &q, int64_t *fc)
         HIP_OR_FAIL(alloc_n(&q.frames, q.frames_count(), fc));
         q.frames_len = q.frames_count();
     }
+    if (q.m1 > 0) {
+        if (!q.c1) HIP_OR_FAIL(alloc_n(&q.c1, n, fc));
+        if (q.plan_len != q.plan_bytes()) {
+            dev_release(q.plan_buf);
+            q.plan_len = 0;
+            HIP_OR_FAIL(alloc_n((char **)&q.plan_buf, q.plan_bytes(), fc));
+            q.plan_len = q.plan_bytes();
+        }
+        HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)q.c1, n, 0u, stream));
+        HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)q.hist(), (size_t)(q.m1 + 1), 0u, stream));
+    }
     if (free_cslots.empty()) return fail(KADABRA_ESTATE, "no free control block");
     q.cslot = free_cslots.back();
     free_cslots.pop_back();
@@ -598,6 +635,9 @@ int Runner::start_query(Query &q, int64_t *fc)
     HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)(d_ctl + q.cslot), sizeof(kd::Control) / 4, 0u, stream));
     q.k = q.merged = q.merged_prev = q.lo = 0;
     q.spec = false;
+    q.first_launched = false;
+    q.plan_tau = 0;
+    for (auto &w : q.work_first) w = 0;
     q.done = false;
     q.status = KADABRA_OK;
     q.decisions.clear();
@@ -686,9 +726,37 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
         ring_pos = (ring_pos + 1) % RING;
         kd::QueryDesc *h = h_qt[r];
         int64_t total = 0;
+        size_t nd = 0;
         Launch L;
+        std::vector<Query *> planned;  // queries whose first phase rides in this launch
         for (size_t x = 0; x < qs.size(); ++x) {
             Query &q = *qs[x];
+            if (q.m1 > 0 && !q.first_launched && !speculative && sample_cap < 0) {
+                // the first phase: its samples are claimed first and add into c1
+                kd::QueryDesc &d = h[nd++];
+                d = kd::QueryDesc{};
+                d.row_ptr = q.gd->d_row_ptr;
+                d.col = q.gd->d_col;
+                d.comp = q.gd->d_comp;
+                d.frames = q.c1;
+                d.ctl = d_ctl + q.cslot;
+                d.seed = q.seed;
+                d.lo = INT64_MIN;  // sample m draws index (uint64) lo + m = kFirstPhaseBase + m
+                d.hi = INT64_MIN + q.m1;
+                d.epoch_len = 1;
+                d.claim_begin = total;
+                d.probe_min = q.probe_min;
+                d.num_arcs = q.gd->arcs;
+                d.n = q.gd->n;
+                d.nframes = 1;
+                d.nsets = 1;
+                d.gate = -1;
+                d.stat_set = kd::kFirstSet;
+                static_assert((uint64_t)INT64_MIN == kd::kFirstPhaseBase, "first-phase index base");
+                total += q.m1;
+                q.first_launched = true;
+                planned.push_back(&q);
+            }
             // the next epl epochs (fewer where omega or the sample cap ends them);
             // callers pass only queries with samples left
             int64_t epoch = q.k, hi = q.lo;
@@ -697,7 +765,9 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
                 hi = q.bound(epoch);
                 if (sample_cap >= 0) hi = std::min(hi, sample_cap);
             }
-            kd::QueryDesc &d = h[x];
+            kd::QueryDesc &d = h[nd++];
+            d = kd::QueryDesc{};
+            d.stat_set = -1;
             d.row_ptr = q.gd->d_row_ptr;
             d.col = q.gd->d_col;
             d.comp = q.gd->d_comp;
@@ -720,10 +790,10 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
             q.lo = hi;
             q.spec = speculative;
         }
-        HIP_OR_FAIL(hipMemcpyAsync(d_qt[r], h, qs.size() * sizeof(kd::QueryDesc), hipMemcpyHostToDevice, stream));
+        HIP_OR_FAIL(hipMemcpyAsync(d_qt[r], h, nd * sizeof(kd::QueryDesc), hipMemcpyHostToDevice, stream));
         kd::SampleArgs sa{};
         sa.q = d_qt[r];
-        sa.nq = (int32_t)qs.size();
+        sa.nq = (int32_t)nd;
         sa.total = total;
         sa.claim = d_claim;
         sa.claim_base = claim_next;
@@ -739,6 +809,21 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
         HIP_OR_FAIL(kd::launch_sample(team, (int)slots, sa, stream));
         HIP_OR_FAIL(hipEventRecord(L.e1, stream));
         pend.push_back(std::move(L));
+        // the balanced constants, from the finished first phase, before any check
+        for (Query *q : planned) {
+            HIP_OR_FAIL(kd::launch_hist(q->c1, q->gd->n, q->hist(), q->m1, d_ctl + q->cslot, stream));
+            kd::PlanArgs pa{};
+            pa.hist = q->hist();
+            pa.lcon = q->lcon();
+            pa.ctl = d_ctl + q->cslot;
+            pa.m1 = q->m1;
+            pa.omega = q->omega;
+            pa.eps = q->eps;
+            pa.delta = q->delta;
+            pa.L = q->L;
+            pa.n = q->gd->n;
+            HIP_OR_FAIL(kd::launch_plan(pa, stream));
+        }
         return KADABRA_OK;
     };
 
@@ -768,6 +853,9 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
                 m.set = q.set_of(epoch);
                 m.frames = q.frames + (size_t)m.set * q.nframes * (size_t)q.gd->n;
                 m.ctl = d_ctl + q.cslot;
+                m.c1 = q.first_launched ? q.c1 : nullptr;
+                m.lcon = q.first_launched ? q.lcon() : nullptr;
+                m.m1 = q.first_launched ? q.m1 : 0;
                 m.tau = tau;
                 m.omega = q.omega;
                 m.L = q.L;
@@ -818,11 +906,12 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
             int dec = 0;
             if (c.err) {
                 static const char *const site[] = {"?", "more BFS levels than the vertex-diameter bound",
-                                                   "no predecessor on a BFS level", "empty frontier"};
+                                                   "no predecessor on a BFS level", "empty frontier",
+                                                   "a first-phase counter above the first-phase samples"};
                 q->status = fail(KADABRA_EDEVICE,
                                  "device-side invariant failure in the sampler (%s) at sample %lld of the "
                                  "query with seed %llu on a graph of %d vertices",
-                                 site[(c.err >= 1 && c.err <= 3) ? c.err : 0], (long long)c.err_sample,
+                                 site[(c.err >= 1 && c.err <= 4) ? c.err : 0], (long long)c.err_sample,
                                  (unsigned long long)q->seed, q->gd->n);
                 status = q->status;
                 pool_dirty = true;
@@ -841,6 +930,8 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
             if (dec || q->status != KADABRA_OK) {
                 q->decision = dec;
                 for (int w = 0; w < kd::ST_COUNT; ++w) q->work[w] = c.stats_total[w];
+                for (int w = 0; w < kd::ST_COUNT; ++w) q->work_first[w] = c.stats[kd::kFirstSet][w];
+                q->plan_tau = c.plan_tau;
                 finished.push_back(q);
             } else {
                 still.push_back(q);
@@ -956,11 +1047,16 @@ struct kadabra_server {
     std::thread worker;
 
     ~kadabra_server();
-    int64_t frame_bytes_of(const GraphData &g) const
+    // device bytes a query holds only while it samples: its frame sets and, for
+    // a balanced run, the first-phase counters and the plan tables
+    int64_t frame_bytes_of(const Query &q) const
     {
-        return (int64_t)g.n * 4 * 2 * params.epochs * (int64_t)params.frames;
+        const int64_t n = q.gd->n;
+        int64_t b = n * 4 * 2 * params.epochs * (int64_t)params.frames;
+        if (q.m1 > 0) b += n * 4 + (int64_t)q.plan_bytes();
+        return b;
     }
-    int64_t charge_of(const GraphData &g) const { return (int64_t)g.n * (4 + 8) + frame_bytes_of(g); }
+    int64_t charge_of(const Query &q) const { return (int64_t)q.gd->n * (4 + 8) + frame_bytes_of(q); }
     void *take_bin(size_t bytes)
     {
         auto it = bins.find(bytes);
@@ -1000,6 +1096,11 @@ struct kadabra_server {
             v->frames = (int32_t *)take_bin(fl * sizeof(int32_t));
             v->frames_len = v->frames ? fl : 0;
             v->scores = (double *)take_bin(n * sizeof(double));
+            if (v->m1 > 0) {
+                v->c1 = (int32_t *)take_bin(n * sizeof(int32_t));
+                v->plan_buf = take_bin(v->plan_bytes());
+                v->plan_len = v->plan_buf ? v->plan_bytes() : 0;
+            }
             out.push_back(v);
         }
         for (auto &b : bins) {
@@ -1034,6 +1135,7 @@ int make_query(Query &q, const GraphData &gd, const Params &p, double eps, doubl
     q.probe_min = p.probe_min;
     q.omega = omega;
     q.L = std::log(4.0 * (double)gd.n / delta);
+    q.m1 = p.balance ? (p.balance_samples ? p.balance_samples : (omega + 19) / 20) : 0;
     q.t_submit = std::chrono::steady_clock::now();
     return KADABRA_OK;
 }
@@ -1074,6 +1176,13 @@ void fill_stats(const Query &q, double ms_total, kadabra_stats *stats)
     stats->ms_total = ms_total;
     stats->ms_sample_kernels = q.ms_kernels;
     stats->sample_launches = q.launches;
+    stats->first_samples = q.first_launched ? q.m1 : 0;
+    stats->plan_tau = q.plan_tau;
+    stats->first_v_exp = q.work_first[kd::ST_VEXP];
+    stats->first_e_scan = q.work_first[kd::ST_ESCAN];
+    stats->first_e_bt = q.work_first[kd::ST_EBT];
+    stats->first_path_interior = q.work_first[kd::ST_INTERIOR];
+    stats->first_disconnected = q.work_first[kd::ST_DISCONN];
 }
 
 int read_result(const Query &q, hipStream_t s, double *scores, int32_t *counts)
@@ -1172,6 +1281,11 @@ void server_main(kadabra_server *s)
         s->put_bin(v->frames, v->frames_len * sizeof(int32_t));
         v->frames = nullptr;
         v->frames_len = 0;
+        s->put_bin(v->c1, v->c1 ? (size_t)v->gd->n * sizeof(int32_t) : 0);
+        s->put_bin(v->plan_buf, v->plan_len);
+        v->c1 = nullptr;
+        v->plan_buf = nullptr;
+        v->plan_len = 0;
         s->in_use -= v->frame_bytes;
         v->charge -= v->frame_bytes;
         s->cv_done.notify_all();
@@ -1375,6 +1489,38 @@ int kadabra_get_decisions(const kadabra_graph *g, int8_t *out, int64_t cap, int6
     if (out)
         for (int64_t k = 0; k < std::min(cap, m); ++k) out[k] = g->q.decisions[(size_t)k];
     if (count) *count = m;
+    return KADABRA_OK;
+}
+
+int kadabra_get_balance(const kadabra_graph *g, double *log_inv_delta_L, double *log_inv_delta_U,
+                        int32_t *first_counts)
+{
+    if (!g) return fail(KADABRA_EINVAL, "null handle");
+    if (!g->have_result) return fail(KADABRA_ESTATE, "no completed run");
+    const Query &q = g->q;
+    const size_t n = (size_t)g->gd.n;
+    if (!q.first_launched) {
+        for (size_t v = 0; v < n; ++v) {
+            if (log_inv_delta_L) log_inv_delta_L[v] = q.L;
+            if (log_inv_delta_U) log_inv_delta_U[v] = q.L;
+            if (first_counts) first_counts[v] = 0;
+        }
+        return KADABRA_OK;
+    }
+    // the counters and the per-count table, then one lookup per vertex
+    std::vector<int32_t> c1(n);
+    std::vector<double> lcon((size_t)(q.m1 + 1) * 2);
+    HIP_OR_FAIL(hipMemcpyAsync(c1.data(), q.c1, n * sizeof(int32_t), hipMemcpyDeviceToHost, g->runner.stream));
+    HIP_OR_FAIL(hipMemcpyAsync(lcon.data(), q.lcon(), lcon.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               g->runner.stream));
+    HIP_OR_FAIL(hipStreamSynchronize(g->runner.stream));
+    for (size_t v = 0; v < n; ++v) {
+        const size_t k = (size_t)c1[v];
+        if (k > (size_t)q.m1) return fail(KADABRA_EDEVICE, "first-phase counter out of range");
+        if (log_inv_delta_L) log_inv_delta_L[v] = lcon[2 * k];
+        if (log_inv_delta_U) log_inv_delta_U[v] = lcon[2 * k + 1];
+        if (first_counts) first_counts[v] = c1[v];
+    }
     return KADABRA_OK;
 }
 
@@ -1638,8 +1784,8 @@ int kadabra_server_submit(kadabra_server *s, int32_t graph_index, double eps, do
     if (!v) return fail(KADABRA_ENOMEM, "host allocation failed");
     const GraphData &gd = *s->graphs[(size_t)graph_index];
     OK_OR_RETURN(make_query(*v, gd, s->params, eps, delta, seed, check_interval));
-    v->charge = s->charge_of(gd);
-    v->frame_bytes = s->frame_bytes_of(gd);
+    v->charge = s->charge_of(*v);
+    v->frame_bytes = s->frame_bytes_of(*v);
     if (v->charge > s->budget)
         return fail(KADABRA_ERANGE, "query needs %lld device bytes, budget is %lld", (long long)v->charge,
                     (long long)s->budget);

@@ -27,6 +27,11 @@ enum StatIdx {
 // epoch e (samples [B_{e-1}, B_e)) uses set e mod nsets, nsets = 2 x (epochs
 // per launch), so a launch and the speculative launch after it never share one.
 constexpr int kMaxSets = 8;
+constexpr int kFirstSet = kMaxSets;  // work-counter set of the balancing first phase
+
+// First-phase sample m of a balanced run is sample index kFirstPhaseBase + m:
+// a range of the random stream that the adaptive samples never reach.
+constexpr uint64_t kFirstPhaseBase = 1ull << 63;
 
 // Device control block of one adaptive run (one per query).
 struct Control {
@@ -35,8 +40,10 @@ struct Control {
                                      // 1 level bound, 2 no predecessor, 3 frontier empty
     int32_t pad;
     int64_t err_sample;              // sample index of the first failure
-    int64_t stats[kMaxSets][ST_COUNT];  // work counters of epochs in flight, by set
+    int64_t stats[kMaxSets + 1][ST_COUNT];  // work counters of epochs in flight, by set;
+                                            // [kFirstSet]: the first phase (never merged)
     int64_t stats_total[ST_COUNT];   // work counters of merged epochs
+    int64_t plan_tau;                // balanced runs: planned sample count t* (0 = no plan)
     int64_t phase_cycles[8];         // per-phase cycles (phase-timer builds only)
 };
 
@@ -74,6 +81,11 @@ struct QueryDesc {
     int32_t nsets;        // frame sets (epoch e uses set e mod nsets)
     int32_t gate;         // -1, or the set of the boundary before lo: if its check found no
                           // violation the run has stopped and this launch does no work for it
+    int32_t stat_set;     // -1: work counters by epoch set; else this set (first phase)
+    int32_t pad;
+    // A first phase is a descriptor with lo = INT64_MIN (its samples' indices
+    // are then kFirstPhaseBase + m as unsigned), nsets = nframes = 1,
+    // frames = c1 and stat_set = kFirstSet.
 };
 
 struct SampleArgs {
@@ -91,6 +103,10 @@ struct MergeDesc {
     int32_t *counts;      // [n] counters of samples [0, tau)
     int32_t *frames;      // the epoch's frame set: [nframes][n]
     Control *ctl;
+    const int32_t *c1;    // balanced runs: first-phase counters [n]; the vertex's constants
+    const double *lcon;   // are lcon[2 c1[v]] (delta_L) and lcon[2 c1[v] + 1] (delta_U);
+                          // null: L for every vertex
+    int64_t m1;           // first-phase samples (rows of lcon: m1 + 1)
     int64_t tau, omega;
     double L, eps;
     int32_t n;
@@ -107,7 +123,24 @@ struct MergeArgs {
     int32_t nblocks;
 };
 
+// Balancing of delta_L(v), delta_U(v) from the first-phase counters c1:
+// hist[k] = #{v : c1[v] = k} (hist zeroed beforehand, m1 + 1 entries; a
+// counter above m1 cannot occur and is reported as device error 4), then
+// one workgroup finds t* and writes lcon[2k], lcon[2k + 1] for k = 0 .. m1
+// and ctl->plan_tau.
+struct PlanArgs {
+    const int32_t *hist;
+    double *lcon;
+    Control *ctl;
+    int64_t m1, omega;
+    double eps, delta, L;
+    int32_t n;
+    int32_t pad;
+};
+
 hipError_t launch_sample(int team, int slots, const SampleArgs &a, hipStream_t s);
+hipError_t launch_hist(const int32_t *c1, int32_t n, int32_t *hist, int64_t m1, Control *ctl, hipStream_t s);
+hipError_t launch_plan(const PlanArgs &a, hipStream_t s);
 hipError_t launch_merge_check(const MergeArgs &a, hipStream_t s);
 int32_t merge_blocks_for(int32_t n);
 hipError_t launch_scores(const int32_t *counts, double *scores, int32_t n, int64_t tau,

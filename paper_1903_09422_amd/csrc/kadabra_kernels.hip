@@ -9,7 +9,8 @@
 //                      (Section 2.3, Appendix C.1).
 //   merge_check_kernel counters += frames of the epoch (frames zeroed), then
 //                      the FP64 stopping rule f, g <= eps of Appendix B for
-//                      every vertex; one violation flag per epoch.
+//                      every vertex (uniform or per-vertex constants); one
+//                      violation flag per epoch.
 //   scores_kernel      b~(v) = c(v) / tau.
 //
 // All path counts and weights are integers, so sums done with atomics in any
@@ -480,6 +481,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
     if (blockIdx.x == 0)
         for (int32_t k = lane; k < a.nq; k += TEAM) {
             const QueryDesc &d = a.q[k];
+            if (d.stat_set >= 0) continue;  // a first phase: no boundary
             for (int64_t e = d.lo / d.epoch_len + 1; e <= (d.hi - 1) / d.epoch_len + 1; ++e)
                 d.ctl->viol[e % d.nsets] = 0;
         }
@@ -530,6 +532,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
         if (qgate >= 0 && qctl->viol[qgate] == 0) continue;
         const int64_t i = qd->lo + (jc - qd->claim_begin);
         const int32_t qpar = (int32_t)((i / qd->epoch_len + 1) % qd->nsets);  // the epoch's set
+        const int32_t qstat = qd->stat_set >= 0 ? qd->stat_set : qpar;       // its work counters
         // graph arrays live in device global memory: say so, so that their
         // loads are global (not flat) instructions
         const gint32_t *const row_ptr = as_global(qd->row_ptr);
@@ -540,10 +543,10 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
         const int64_t probe_min = qd->probe_min, num_arcs = qd->num_arcs;
         int32_t *const frame =
             qd->frames + ((size_t)qpar * qd->nframes + (size_t)(blockIdx.x % qd->nframes)) * (size_t)nv;
-        if (qctl != acc_ctl || qpar != acc_par) {
+        if (qctl != acc_ctl || qstat != acc_par) {
             flush();
             acc_ctl = qctl;
-            acc_par = qpar;
+            acc_par = qstat;
         }
 #ifdef KADABRA_PHASE_TIMERS
         ph_ctl = qctl;
@@ -1055,18 +1058,20 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
 // and evaluate the stopping rule of Appendix B on exactly samples [0, tau):
 //   f = (L/tau) (1/3 - w/tau + sqrt((1/3 - w/tau)^2 + 2 b w / L))
 //   g = (L/tau) (1/3 + w/tau + sqrt((1/3 + w/tau)^2 + 2 b w / L))
-// b = c / tau, w = omega, L = log(1/delta_L).  IEEE double in this exact
-// order; the file is compiled without floating-point contraction.
+// b = c / tau, w = omega, L = log(1/delta_L(v)) in f and log(1/delta_U(v))
+// in g.  IEEE double in this exact order; the file is compiled without
+// floating-point contraction.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void stop_fg(int32_t c, double t, double w, double L, double *f,
-                                        double *g)
+__device__ __forceinline__ void stop_fg(int32_t c, double t, double w, double LL, double LU,
+                                        double *f, double *g)
 {
     const double b = (double)c / t;
     const double af = 1.0 / 3.0 - w / t;
     const double ag = 1.0 / 3.0 + w / t;
-    const double q = 2.0 * b * w / L;
-    *f = (L / t) * (af + sqrt(af * af + q));
-    *g = (L / t) * (ag + sqrt(ag * ag + q));
+    const double qf = 2.0 * b * w / LL;
+    const double qg = 2.0 * b * w / LU;
+    *f = (LL / t) * (af + sqrt(af * af + qf));
+    *g = (LU / t) * (ag + sqrt(ag * ag + qg));
 }
 
 constexpr int32_t MERGE_BLOCK = 256;
@@ -1103,8 +1108,15 @@ __global__ __launch_bounds__(MERGE_BLOCK) void merge_check_kernel(MergeArgs a)
         }
         M.counts[v] = c;
         if (M.do_check) {
+            double LL = M.L, LU = M.L;
+            if (M.lcon) {  // balanced: the constants of the vertex's first-phase count
+                int64_t k = M.c1[v];
+                k = k < 0 ? 0 : (k > M.m1 ? M.m1 : k);  // in range (else device error 4 is set)
+                LL = M.lcon[2 * k];
+                LU = M.lcon[2 * k + 1];
+            }
             double fv, gv;
-            stop_fg(c, t, w, M.L, &fv, &gv);
+            stop_fg(c, t, w, LL, LU, &fv, &gv);
             if (!(fv <= M.eps) || !(gv <= M.eps)) viol = 1;
         }
     }
@@ -1129,7 +1141,7 @@ __global__ void eval_fg_kernel(const int32_t *counts, int32_t n, int64_t tau, in
 {
     for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < (size_t)n;
          v += (size_t)gridDim.x * blockDim.x)
-        stop_fg(counts[v], (double)tau, (double)omega, L, &f[v], &g[v]);
+        stop_fg(counts[v], (double)tau, (double)omega, L, L, &f[v], &g[v]);
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, size_t count, uint32_t value)
