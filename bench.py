@@ -71,6 +71,8 @@ def main() -> int:
     ap.add_argument("--overlap", type=int, default=1)
     ap.add_argument("--epochs-per-launch", type=int, default=2)
     ap.add_argument("--probe-min", type=int, default=-1)
+    ap.add_argument("--balanced-steps", type=int, default=10,
+                    help="queries of the balanced leg (per-vertex delta_L, delta_U); 0: skip it")
     ap.add_argument("--cpu-repeats", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--traffic-json", default=None,
@@ -193,11 +195,31 @@ def main() -> int:
             "algorithmic_bytes_per_launch": kern_bytes / max(launches, 1),
         },
     }
+    if args.balanced_steps > 0:
+        out["balanced"] = balanced_leg(dev, step, stream, args, dt * 1e3 / args.steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, eps, delta, args.seed, n_check, args.cpu_repeats)
     dev.close()
     print(json.dumps(out))
     return 0
+
+
+def balanced_leg(dev, step, stream, args, uniform_ms):
+    """The same query with balanced delta_L(v), delta_U(v): time per query
+    (first phase, plan and adaptive loop) beside the uniform constants'."""
+    dev.set_param("balance", 1)
+    step()
+    stream.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.balanced_steps):
+        st = step()
+        stream.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.balanced_steps
+    dev.set_param("balance", 0)
+    drawn = int(st["tau"] + st["first_samples"])
+    return {"ms_per_query": ms, "uniform_ms_per_query": uniform_ms, "speedup": uniform_ms / ms,
+            "tau": int(st["tau"]), "first_samples": int(st["first_samples"]),
+            "plan_tau": int(st["plan_tau"]), "samples_per_s": drawn / (ms * 1e-3)}
 
 
 def bench_batch(args) -> int:
@@ -379,17 +401,17 @@ def bench_serve(args) -> int:
 COPY_BYTES = 1 << 30
 PMC_CMDS = {
     "trace": "rocprofv3 --kernel-trace --stats -f csv -d DIR/ktrace -o bench -- "
-             "python3 bench.py --workload {w} --steps 5 --warmup 1 --no-cpu",
+             "python3 bench.py --workload {w} --steps 5 --warmup 1 --no-cpu --balanced-steps 0",
     "fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d DIR/pmc_FETCH_SIZE -o bench -- "
-             "python3 bench.py --workload {w} --steps 2 --warmup 0 --no-cpu",
+             "python3 bench.py --workload {w} --steps 2 --warmup 0 --no-cpu --balanced-steps 0",
     "write": "rocprofv3 --pmc WRITE_SIZE -f csv -d DIR/pmc_WRITE_SIZE -o bench -- "
-             "python3 bench.py --workload {w} --steps 2 --warmup 0 --no-cpu",
+             "python3 bench.py --workload {w} --steps 2 --warmup 0 --no-cpu --balanced-steps 0",
     "copy_fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d DIR/pmc_copy_FETCH_SIZE -o copy -- "
                   "python3 bench.py --calibrate-copy 1073741824",
     "copy_write": "rocprofv3 --pmc WRITE_SIZE -f csv -d DIR/pmc_copy_WRITE_SIZE -o copy -- "
                   "python3 bench.py --calibrate-copy 1073741824",
     "l2": "rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum -f csv -d DIR/pmc_tcc -o bench -- "
-          "python3 bench.py --workload {w} --steps 2 --warmup 0 --no-cpu",
+          "python3 bench.py --workload {w} --steps 2 --warmup 0 --no-cpu --balanced-steps 0",
 }
 
 
