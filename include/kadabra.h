@@ -125,6 +125,11 @@ int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr,
  *                     degree sums reaches four times the arc count.
  *   "test_fail_alloc" k >= 1: the k-th device allocation of the next run's
  *                     buffers fails with ENOMEM (failure-path testing); 0: off.
+ *   "test_plan_cache_rows" k >= 1: the balancing plan keeps at most k nonzero
+ *                     rows of the first-phase count histogram in LDS (more
+ *                     rows than that are read from device memory at every
+ *                     bisection step: the path taken when they do not fit);
+ *                     0 (default): up to 4096.  Never changes results.
  *   "test_level_cap"  k >= 3: the sampler is given room for only k BFS levels
  *                     per side, so samples needing more fail its level-bound
  *                     check and the run ends with EDEVICE (failure-path

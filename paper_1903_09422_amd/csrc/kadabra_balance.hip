@@ -30,33 +30,43 @@ namespace kd {
 
 constexpr double kBalanceFloor = 0.1;  // share of the budget spread evenly
 constexpr int HIST_BLOCK = 256;
+constexpr int HIST_GRID = 256;   // one workgroup per CU: few global atomics per bin
+constexpr int HIST_BINS = 256;   // counts below this are binned in LDS first
 constexpr int PLAN_BLOCK = 1024;
+constexpr int PLAN_CACHE = 4096; // nonzero histogram rows kept in LDS during the search
 
-// hist[k] += 1 for every vertex with c1 = k.  Most vertices have c1 = 0: a
-// wavefront adds its zeros with one atomic.
+// hist[k] += 1 for every vertex with c1 = k.  Most vertices have c1 = 0 and
+// the counts are small: a workgroup bins counts below HIST_BINS in LDS (a
+// wavefront adds its zeros with one LDS atomic) and adds each nonzero bin to
+// hist once.
 __global__ __launch_bounds__(HIST_BLOCK) void hist_kernel(const int32_t *c1, int32_t n, int32_t *hist,
                                                           int64_t m1, Control *ctl)
 {
+    __shared__ int32_t bins[HIST_BINS];
+    for (int k = threadIdx.x; k < HIST_BINS; k += HIST_BLOCK) bins[k] = 0;
+    __syncthreads();
     const size_t stride = (size_t)gridDim.x * HIST_BLOCK;
-    const size_t base0 = (size_t)blockIdx.x * HIST_BLOCK;
     const int lane = threadIdx.x & 63;
-    // every lane of a wavefront runs the same number of iterations (the
-    // ballot below needs the whole wavefront)
-    for (size_t base = base0; base < (size_t)n; base += stride) {
+    // every lane of a wavefront runs the same iterations (the ballot needs them all)
+    for (size_t base = (size_t)blockIdx.x * HIST_BLOCK; base < (size_t)n; base += stride) {
         const size_t v = base + threadIdx.x;
         const int32_t k = v < (size_t)n ? c1[v] : -1;
-        const bool zero = v < (size_t)n && k == 0;
-        const uint64_t zeros = __ballot(zero);
-        if (lane == 0 && zeros) atomicAdd(&hist[0], (int32_t)__popcll(zeros));
+        const uint64_t zeros = __ballot(v < (size_t)n && k == 0);
+        if (lane == 0 && zeros) atomicAdd(&bins[0], (int32_t)__popcll(zeros));
         if (v < (size_t)n && k != 0) {
             if (k < 0 || (int64_t)k > m1) {
                 if (atomicCAS(&ctl->err, 0, 4) == 0)
                     atomicExch((unsigned long long *)&ctl->err_sample, (unsigned long long)v);
+            } else if (k < HIST_BINS) {
+                atomicAdd(&bins[k], 1);
             } else {
                 atomicAdd(&hist[k], 1);
             }
         }
     }
+    __syncthreads();
+    for (int k = threadIdx.x; k < HIST_BINS; k += HIST_BLOCK)
+        if (bins[k]) atomicAdd(&hist[k], bins[k]);  // a nonzero bin has k <= m1
 }
 
 __device__ __forceinline__ void plan_lfg(double b, double t, double w, double eps, double *lf, double *lg)
@@ -86,10 +96,40 @@ __device__ __forceinline__ double plan_block_sum(double x, double *red)
 __global__ __launch_bounds__(PLAN_BLOCK) void plan_kernel(PlanArgs a)
 {
     __shared__ double red[PLAN_BLOCK / 64];
+    __shared__ double cb[PLAN_CACHE];   // planning values b_p of the nonzero rows, ascending k
+    __shared__ int32_t ch[PLAN_CACHE];  // their vertex counts
+    __shared__ int32_t wsum[PLAN_BLOCK / 64];
     const double beta = kBalanceFloor;
     const double target = (1.0 - beta) * (a.delta / 2.0) * (1.0 - 1e-6);
     const double w = (double)a.omega;
     const double m1 = (double)a.m1;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+
+    // the nonzero rows of the histogram, in ascending k, into LDS (all of
+    // them if they fit; otherwise the search reads the histogram itself)
+    int32_t rows = 0;
+    for (int64_t base = 0; base <= a.m1; base += PLAN_BLOCK) {
+        const int64_t k = base + threadIdx.x;
+        const int32_t h = k <= a.m1 ? a.hist[k] : 0;
+        const uint64_t nz = __ballot(h != 0);
+        __syncthreads();  // the previous chunk's reads of wsum are done
+        if (lane == 0) wsum[wv] = (int32_t)__popcll(nz);
+        __syncthreads();
+        int32_t before = 0, chunk = 0;
+        for (int j = 0; j < PLAN_BLOCK / 64; ++j) {
+            before += j < wv ? wsum[j] : 0;
+            chunk += wsum[j];
+        }
+        const int32_t pos = rows + before + (int32_t)__popcll(nz & ((1ull << lane) - 1));
+        if (h != 0 && pos < PLAN_CACHE) {
+            cb[pos] = ((double)k + 1.0) / m1;
+            ch[pos] = h;
+        }
+        rows += chunk;
+    }
+    const bool cached = rows <= (a.cache_rows > 0 ? a.cache_rows : PLAN_CACHE);
+    __syncthreads();
+
     // bisection for t*: S(t) is the same value in every thread, so every
     // thread takes the same branch and runs the same number of rounds
     int64_t lo = 1, hi = a.omega;
@@ -97,12 +137,20 @@ __global__ __launch_bounds__(PLAN_BLOCK) void plan_kernel(PlanArgs a)
         const int64_t mid = lo + (hi - lo) / 2;
         const double t = (double)mid;
         double part = 0.0;
-        for (int64_t k = threadIdx.x; k <= a.m1; k += PLAN_BLOCK) {
-            const int32_t h = a.hist[k];
-            if (h == 0) continue;
-            double lf, lg;
-            plan_lfg(((double)k + 1.0) / m1, t, w, a.eps, &lf, &lg);
-            part += (double)h * (exp(-lf) + exp(-lg));
+        if (cached) {
+            for (int32_t j = threadIdx.x; j < rows; j += PLAN_BLOCK) {
+                double lf, lg;
+                plan_lfg(cb[j], t, w, a.eps, &lf, &lg);
+                part += (double)ch[j] * (exp(-lf) + exp(-lg));
+            }
+        } else {
+            for (int64_t k = threadIdx.x; k <= a.m1; k += PLAN_BLOCK) {
+                const int32_t h = a.hist[k];
+                if (h == 0) continue;
+                double lf, lg;
+                plan_lfg(((double)k + 1.0) / m1, t, w, a.eps, &lf, &lg);
+                part += (double)h * (exp(-lf) + exp(-lg));
+            }
         }
         if (plan_block_sum(part, red) <= target) hi = mid;
         else lo = mid + 1;
@@ -128,7 +176,7 @@ hipError_t launch_hist(const int32_t *c1, int32_t n, int32_t *hist, int64_t m1, 
 {
     if (n <= 0) return hipSuccess;
     size_t g = ((size_t)n + HIST_BLOCK - 1) / HIST_BLOCK;
-    if (g > 4096) g = 4096;
+    if (g > HIST_GRID) g = HIST_GRID;
     hipLaunchKernelGGL(hist_kernel, dim3((unsigned)g), dim3(HIST_BLOCK), 0, s, c1, n, hist, m1, ctl);
     return hipGetLastError();
 }

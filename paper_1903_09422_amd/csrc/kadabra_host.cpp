@@ -192,6 +192,7 @@ struct Params {
     int64_t balance_samples = 0;  // first-phase samples; 0: ceil(omega / 20)
     int64_t fail_alloc = 0;  // test hook
     int32_t level_cap = 0;   // test hook: 0, or a smaller level capacity per side
+    int32_t plan_cache = 0;  // test hook: 0, or fewer histogram rows kept in LDS by the plan search
 };
 
 int set_common_param(Params &p, const char *key, int64_t value, bool *known)
@@ -227,6 +228,9 @@ int set_common_param(Params &p, const char *key, int64_t value, bool *known)
         if (value < 0 || value > kMaxFirstPhase)
             return fail(KADABRA_EINVAL, "balance_samples must be in [0, %lld]", (long long)kMaxFirstPhase);
         p.balance_samples = value;
+    } else if (!strcmp(key, "test_plan_cache_rows")) {
+        if (value < 0 || value > (1 << 20)) return fail(KADABRA_EINVAL, "test_plan_cache_rows must be in [0, 2^20]");
+        p.plan_cache = (int32_t)value;
     } else if (!strcmp(key, "test_fail_alloc")) {
         if (value < 0) return fail(KADABRA_EINVAL, "test_fail_alloc must be >= 0");
         p.fail_alloc = value;
@@ -252,6 +256,7 @@ int get_common_param(const Params &p, const char *key, int64_t *value)
     else if (!strcmp(key, "balance")) *value = p.balance;
     else if (!strcmp(key, "balance_samples")) *value = p.balance_samples;
     else if (!strcmp(key, "test_level_cap")) *value = p.level_cap;
+    else if (!strcmp(key, "test_plan_cache_rows")) *value = p.plan_cache;
     else return 1;
     return 0;
 }
@@ -731,7 +736,11 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
         std::vector<Query *> planned;  // queries whose first phase rides in this launch
         for (size_t x = 0; x < qs.size(); ++x) {
             Query &q = *qs[x];
+            int epochs_now = q.epl;
             if (q.m1 > 0 && !q.first_launched && !speculative && sample_cap < 0) {
+                // a balanced run is planned to stop early: its first launch
+                // carries one check interval, so that the first check comes
+                // as soon as possible
                 // the first phase: its samples are claimed first and add into c1
                 kd::QueryDesc &d = h[nd++];
                 d = kd::QueryDesc{};
@@ -756,11 +765,12 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
                 total += q.m1;
                 q.first_launched = true;
                 planned.push_back(&q);
+                epochs_now = 1;
             }
             // the next epl epochs (fewer where omega or the sample cap ends them);
             // callers pass only queries with samples left
             int64_t epoch = q.k, hi = q.lo;
-            for (int j = 0; j < q.epl && hi < q.omega && (sample_cap < 0 || hi < sample_cap); ++j) {
+            for (int j = 0; j < epochs_now && hi < q.omega && (sample_cap < 0 || hi < sample_cap); ++j) {
                 ++epoch;
                 hi = q.bound(epoch);
                 if (sample_cap >= 0) hi = std::min(hi, sample_cap);
@@ -822,6 +832,7 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
             pa.delta = q->delta;
             pa.L = q->L;
             pa.n = q->gd->n;
+            pa.cache_rows = p.plan_cache;
             HIP_OR_FAIL(kd::launch_plan(pa, stream));
         }
         return KADABRA_OK;

@@ -135,7 +135,7 @@ struct PlanArgs {
     int64_t m1, omega;
     double eps, delta, L;
     int32_t n;
-    int32_t pad;
+    int32_t cache_rows;   // test hook: > 0 caps the histogram rows the search keeps in LDS
 };
 
 hipError_t launch_sample(int team, int slots, const SampleArgs &a, hipStream_t s);

@@ -85,7 +85,8 @@ def test_balanced_mappings_and_epochs():
     want = oracle.run(g, eps, 0.1, 9, n_check, first_samples=-1)
     for params in ({"epochs_per_launch": 1}, {"epochs_per_launch": 3, "overlap": 0},
                    {"epochs_per_launch": 4}, {"frames": 3}, {"team": 128, "slots": 50},
-                   {"team": 512}, {"probe_min": 0}):
+                   {"team": 512}, {"probe_min": 0},
+                   {"test_plan_cache_rows": 1}, {"test_plan_cache_rows": 5}):
         print("case balanced rmat11 mapping", params, flush=True)
         got, consts = balanced_run(g, eps, 0.1, 9, n_check, **params)
         assert_same_balanced(got, consts, want)
