@@ -448,6 +448,24 @@ __device__ __forceinline__ void pick_by_id_prefix(const int32_t *sv, const Sigma
     }
 }
 
+// Zeroes the code word and sigma of every vertex in ball[0, len).
+template <int TEAM>
+__device__ __forceinline__ void clear_ball(const int32_t *ball, int32_t len, uint32_t *code, Sigma *sig)
+{
+    constexpr int U = 4;
+    for (int32_t k0 = threadIdx.x; k0 < len; k0 += U * TEAM) {
+        int32_t w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) w[u] = (k0 + u * TEAM < len) ? ball[k0 + u * TEAM] : -1;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (w[u] >= 0) {
+                code[w[u] >> 3] = 0u;
+                sig[w[u]] = Sigma{0u, 0u};
+            }
+    }
+}
+
 // Wave/workgroup-per-sample sampler.  Every lane of the team runs the same
 // control flow; per-sample scalars live in registers (uniform) or LDS.
 template <int TEAM>
@@ -559,7 +577,11 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
         const int32_t s = (int32_t)__umul64hi(u_s, (uint64_t)nv);
         int32_t t = (int32_t)__umul64hi(u_t, (uint64_t)(nv - 1));
         t += (t >= s) ? 1 : 0;
-        if (comp[s] != comp[t]) {  // Appendix C.1: no search across components
+        // the component test and both rows' bounds, loaded together
+        const int32_t cs = comp[s], ct = comp[t];
+        const int32_t rs_s = row_ptr[s], re_s = row_ptr[s + 1];
+        const int32_t rs_t = row_ptr[t], re_t = row_ptr[t + 1];
+        if (cs != ct) {  // Appendix C.1: no search across components
             if (lane == 0) sm.acc[ST_DISCONN] += 1;
             continue;
         }
@@ -583,8 +605,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
         // per-side BFS state (uniform across the team; side X selected by value)
         int32_t lvl0 = 0, lvl1 = 0;
         int32_t flo0 = 0, flo1 = 0, fhi0 = 1, fhi1 = 1;  // frontier = ball[flo, fhi)
-        const int32_t rs_s = row_ptr[s], rs_t = row_ptr[t];
-        int64_t dsum0 = row_ptr[s + 1] - rs_s, dsum1 = row_ptr[t + 1] - rs_t;
+        int64_t dsum0 = re_s - rs_s, dsum1 = re_t - rs_t;
         bool fc0 = true, fc1 = true;  // the side's frontier is in the LDS cache
         if (lane == 0) {
             sm.frs[0][0] = rs_s;
@@ -596,6 +617,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
         }
         u128 fmass0 = 1, fmass1 = 1;  // sum of the frontier's sigma
         int X = 0, nN = 0, nM = 0;
+        bool meet_staged = false;  // the meeting set is sm.sv[0, nM) (a probe level that fit)
         int fail_site = 0;
         bool ok = true, retry = false;
         int lp = 0;  // which append counters this BFS iteration uses (the other ones are zero)
@@ -791,19 +813,35 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 T::sync();
             }
             PHASE_MARK(2);
-            if (nM > 0) break;
+            if (nM > 0) {
+                // on a probe level only meeting vertices were claimed, so the
+                // new level (staged in LDS when it fits) is the meeting set
+                meet_staged = probe && nN == nM && nN <= STAGE;
+                break;
+            }
             // advance side X: its frontier becomes the new level (ids staged in
             // LDS by the claims when they fit; a one-chunk level is cached)
             uint64_t ds = 0;
             u128 ms = 0;
             const bool staged_new = nN <= STAGE, cache_new = nN <= TEAM;
-            for (int32_t k = lane; k < nN; k += TEAM) {
+            // two vertices per lane and pass: both loads issued before either is used
+            for (int32_t k = lane; k < nN; k += 2 * TEAM) {
+                const int32_t k2 = k + TEAM;
+                const bool two = k2 < nN;
                 const int32_t w = staged_new ? sm.sv[k] : ballx[base_new + k];
-                const int32_t rs = row_ptr[w], dg = row_ptr[w + 1] - rs;
+                const int32_t w2 = two ? (staged_new ? sm.sv[k2] : ballx[base_new + k2]) : w;
+                const int32_t rs = row_ptr[w], re = row_ptr[w + 1];
+                const int32_t rs2 = row_ptr[w2], re2 = row_ptr[w2 + 1];
                 const Sigma m = sigx[w];
+                const Sigma m2 = sigx[w2];
+                const int32_t dg = re - rs;
                 ds += (uint64_t)dg;
                 ms += to128(m);
-                if (cache_new) {
+                if (two) {
+                    ds += (uint64_t)(re2 - rs2);
+                    ms += to128(m2);
+                }
+                if (cache_new) {  // then nN <= TEAM: k is the only vertex of the lane
                     sm.frs[X][k] = rs;
                     sm.fdg[X][k] = dg;
                     sm.fsg[X][k] = m;
@@ -835,7 +873,35 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
             // -- meeting vertex: P(v) = sigma_s(v) sigma_t(v), ascending id ----
             int32_t v;
             if (nM == 1) {
-                v = meet[0];
+                v = meet_staged ? sm.sv[0] : meet[0];
+            } else if (nM <= TEAM) {
+                // one meeting vertex per lane: its product stays in registers
+                // between the maximum and the weight
+                const bool has = lane < nM;
+                int32_t w = 0;
+                U256 p{0, 0};
+                if (has) {
+                    w = meet_staged ? sm.sv[lane] : meet[lane];
+                    p = mul_128x128(to128(sig0[w]), to128(sig1[w]));
+                }
+                const U256 pm = T::max_u256(p, redA);
+                const int shp = max(0, bitw256(pm) - WEIGHT_BITS);
+                const uint64_t wt = has ? ceil_shr256(p, shp) : 0u;
+                if (has) {
+                    sm.sv[lane] = w;
+                    sm.sw[lane] = Sigma{wt, 0u};
+                }
+                const uint64_t tot = T::sum_u64(wt, redB);
+                const uint64_t r = __umul64hi(philox_u64(seed, (uint64_t)i, 1u), tot);
+                // rank by scanning the staged set: the element whose
+                // ascending-id inclusive prefix first exceeds r
+                if (lane == 0) sm.pick = -1;
+                __syncthreads();  // also: the staged weights are visible
+                pick_by_id_prefix<TEAM>(sm.sv, sm.sw, nM, (u128)r, &sm.pick);
+                __syncthreads();
+                v = uniform_i32(sm.pick);
+                // every wave holds v before backtracking resets sm.pick
+                __syncthreads();
             } else {
                 const bool staged = nM <= STAGE;
                 U256 pm{0, 0};
@@ -863,15 +929,14 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     vmax = max(vmax, w);
                 }
                 tot = T::sum_u64(tot, redB);
-                // team min / max of the ids (as maxima of n - id and id + 1),
-                // needed by the binary search over ids only
+                // team min / max of the ids (as maxima of n - id and id + 1)
                 uint64_t mn = (uint64_t)(uint32_t)(nv - vmin), mx = (uint64_t)(uint32_t)(vmax + 1);
 #pragma unroll
                 for (int o = 32; o > 0; o >>= 1) {
                     mn = max(mn, (uint64_t)__shfl_xor(mn, o, 64));
                     mx = max(mx, (uint64_t)__shfl_xor(mx, o, 64));
                 }
-                if (T::WAVES > 1 && nM > TEAM) {
+                if (T::WAVES > 1) {
                     uint64_t *const rr = redA;  // then a sync
                     const int wv = lane >> 6;
                     if ((lane & 63) == 0) {
@@ -886,35 +951,23 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 }
                 T::sync();  // staged weights visible to the whole team
                 const uint64_t r = __umul64hi(philox_u64(seed, (uint64_t)i, 1u), tot);
-                if (nM <= TEAM) {
-                    // rank by scanning the staged set: the element whose
-                    // ascending-id inclusive prefix first exceeds r
-                    if (lane == 0) sm.pick = -1;
-                    __syncthreads();
-                    pick_by_id_prefix<TEAM>(sm.sv, sm.sw, nM, (u128)r, &sm.pick);
-                    __syncthreads();
-                    v = uniform_i32(sm.pick);
-                    // every wave holds v before backtracking resets sm.pick
-                    __syncthreads();
-                } else {
-                    // smallest id v whose inclusive prefix (ascending ids) exceeds r
-                    int32_t lo = nv - (int32_t)mn, hi = (int32_t)mx - 1;
-                    int32_t it = 0;  // consecutive sums alternate their scratch
-                    while (lo < hi) {
-                        const int32_t mid = lo + ((hi - lo) >> 1);
-                        uint64_t part = 0;
-                        if (staged) {
-                            for (int32_t k = lane; k < nM; k += TEAM)
-                                part += (sm.sv[k] <= mid) ? sm.sw[k].lo : 0u;
-                        } else {
-                            for (int32_t k = lane; k < nM; k += TEAM)
-                                part += (meet[k] <= mid) ? meetw[k] : 0u;
-                        }
-                        part = T::sum_u64(part, (it++ & 1) ? redB : redA);
-                        if (part > r) hi = mid; else lo = mid + 1;
+                // smallest id v whose inclusive prefix (ascending ids) exceeds r
+                int32_t lo = nv - (int32_t)mn, hi = (int32_t)mx - 1;
+                int32_t it = 0;  // consecutive sums alternate their scratch
+                while (lo < hi) {
+                    const int32_t mid = lo + ((hi - lo) >> 1);
+                    uint64_t part = 0;
+                    if (staged) {
+                        for (int32_t k = lane; k < nM; k += TEAM)
+                            part += (sm.sv[k] <= mid) ? sm.sw[k].lo : 0u;
+                    } else {
+                        for (int32_t k = lane; k < nM; k += TEAM)
+                            part += (meet[k] <= mid) ? meetw[k] : 0u;
                     }
-                    v = lo;
+                    part = T::sum_u64(part, (it++ & 1) ? redB : redA);
+                    if (part > r) hi = mid; else lo = mid + 1;
                 }
+                v = lo;
             }
             PHASE_MARK(3);
             // v's distances: one more than side X's frontier level, side Y's level
@@ -1031,17 +1084,10 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
 
         // -- clear what this sample touched ----------------------------------
         // a code word holds only codes of vertices reached by this sample, so
-        // zeroing whole words restores the all-zero state
-        for (int32_t k = lane; k < bend0; k += TEAM) {
-            const int32_t w = ball0[k];
-            code[w >> 3] = 0u;
-            sig0[w] = Sigma{0u, 0u};
-        }
-        for (int32_t k = lane; k < bend1; k += TEAM) {
-            const int32_t w = ball1[k];
-            code[w >> 3] = 0u;
-            sig1[w] = Sigma{0u, 0u};
-        }
+        // zeroing whole words restores the all-zero state; four list entries
+        // are loaded before their stores
+        clear_ball<TEAM>(ball0, bend0, code, sig0);
+        clear_ball<TEAM>(ball1, bend1, code, sig1);
         PHASE_MARK(5);
     }
     flush();
