@@ -1023,6 +1023,22 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                             done = true;
                         }
                     }
+                    if (!done && deg <= TEAM) {
+                        // a row of at most TEAM arcs: lane k holds arc k; the code
+                        // word and sigma of its neighbour are loaded together, and
+                        // the lane whose prefix interval holds r is the pick
+                        const bool mine = lane < deg;
+                        const int32_t p = mine ? col[rs + lane] : 0;
+                        const uint32_t cw = code[p >> 3];
+                        const Sigma sp = sg[p];
+                        const u128 part = (mine && ((cw >> code_shift(p, side)) & 3u) == want) ? to128(sp)
+                                                                                               : (u128)0;
+                        u128 tot;
+                        const u128 ex_pre = T::excl_scan_u128(part, &tot, redA);
+                        const u128 r = mulhi_64x128(U, tot);
+                        if (part != 0 && ex_pre <= r && r < ex_pre + part) sm.pick = p;
+                        done = true;
+                    }
                     if (!done) {
                         // scan x's row: lane owns the contiguous arc segment [e0, e1)
                         const int32_t e0 = rs + (int32_t)(((int64_t)deg * lane) / TEAM);
