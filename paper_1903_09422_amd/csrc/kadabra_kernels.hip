@@ -448,6 +448,33 @@ __device__ __forceinline__ void pick_by_id_prefix(const int32_t *sv, const Sigma
     }
 }
 
+// An open-addressing set of vertex ids in LDS: mask + 1 slots (a power of
+// two), -1 = empty, linear probing.  Filled to at most half, so every probe
+// sequence ends.
+__device__ __forceinline__ int32_t hash_slot(int32_t w, int32_t mask)
+{
+    return (int32_t)(((uint32_t)w * 0x9E3779B1u) >> 16) & mask;
+}
+__device__ __forceinline__ void hash_insert(int32_t *keys, int32_t mask, int32_t w)
+{
+    int32_t h = hash_slot(w, mask);
+    while (atomicCAS(&keys[h], -1, w) != -1) h = (h + 1) & mask;
+}
+__device__ __forceinline__ int32_t hash_find(const int32_t *keys, int32_t mask, int32_t w)
+{
+    int32_t h = hash_slot(w, mask);
+    while (keys[h] != w) h = (h + 1) & mask;
+    return h;
+}
+
+// *p += v for a 128-bit count in LDS
+__device__ __forceinline__ void lds_add128(Sigma *p, Sigma v)
+{
+    const uint64_t o = atomicAdd((unsigned long long *)&p->lo, (unsigned long long)v.lo);
+    const uint64_t hi = v.hi + ((o + v.lo) < o ? 1u : 0u);
+    if (hi) atomicAdd((unsigned long long *)&p->hi, (unsigned long long)hi);
+}
+
 // Zeroes the code word and sigma of every vertex in ball[0, len).
 template <int TEAM>
 __device__ __forceinline__ void clear_ball(const int32_t *ball, int32_t len, uint32_t *code, Sigma *sig)
@@ -659,6 +686,21 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
             int32_t *const cnt_new = &sm.nnext[lp];
             int32_t *const cnt_meet = &sm.nmeet[lp];
             const bool fcx = X ? fc1 : fc0;  // then the frontier is one chunk
+            // Small full levels may add sigma in LDS: the frontier is one chunk
+            // and its arcs one round per lane.  A claim's winner enters its
+            // vertex into an LDS hash set whose slot indexes an LDS count (the
+            // keys take side X's frontier cache, unused until this level's
+            // bookkeeping rewrites it).  After a barrier, if the new level has
+            // at most HMAX vertices, every arc into it adds there and each new
+            // vertex's count is stored once: no sigma atomics and no read-back
+            // in the level's chain of global accesses.  Otherwise the arcs kept
+            // in registers add into global memory as usual.  Not on probe levels
+            // (a retry reads the cache again) nor when the level may rescale.
+            const bool lds_try = !probe && fhix - flox <= TEAM && dsx <= (int64_t)ARCS * TEAM &&
+                                 bitw128(X ? fmass1 : fmass0) <= SIGMA_BITS;
+            int32_t *const hkeys = reinterpret_cast<int32_t *>(&sm.fsg[X][0]);  // 4 TEAM >= STAGE ints
+            constexpr int32_t HMASK = STAGE - 1;
+            constexpr int32_t HMAX = STAGE / 2;  // at most half of the slots are filled
             for (int32_t c0 = flox; c0 < fhix; c0 += TEAM) {
                 const int32_t idx = c0 + lane;
                 int32_t dg = 0;
@@ -674,6 +716,12 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                         sm.crs[lane] = rs;
                         sm.cm[lane] = sigx[u];
                     }
+                }
+                if (lds_try) {
+                    // each lane empties the key slots of its own cache entry (read above)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) hkeys[4 * lane + j] = -1;
+                    for (int32_t h = lane; h < STAGE; h += TEAM) sm.sw[h] = Sigma{0u, 0u};
                 }
                 int32_t tot;
                 const int32_t ex = T::excl_scan_i32(dg, &tot, redA);
@@ -698,10 +746,13 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     }
                     return own;
                 };
-                for (int32_t e = lane; e < tot; e += ARCS * TEAM) {
+                // One round: arcs e, e + TEAM, ... (up to ARCS) of this lane --
+                // owners, column entries, code words, claims and appends.  wv,
+                // ow and add receive the arcs and which of them enter the new level.
+                auto claim_round = [&](int32_t e, int32_t (&wv)[ARCS], int32_t (&ow)[ARCS], bool (&add)[ARCS]) {
                     // owners and arc positions (LDS only); an arc past the end
                     // repeats arc e so that every load below is unconditional
-                    int32_t ow[ARCS], ai[ARCS], wv[ARCS];
+                    int32_t ai[ARCS];
                     uint32_t wd[ARCS];
 #pragma unroll
                     for (int k = 0; k < ARCS; ++k) {
@@ -734,7 +785,6 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
 #pragma unroll
                     for (int k = 0; k < ARCS; ++k)
                         old[k] = cand[k] ? wg_or_u32(&code[wv[k] >> 3], code_new << code_shift(wv[k], X)) : 0u;
-                    bool add[ARCS];
 #pragma unroll
                     for (int k = 0; k < ARCS; ++k) {
                         const int32_t w = wv[k];
@@ -748,14 +798,18 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                         if (claimed) {
                             ballx[base_new + p] = w;
                             if (p < STAGE) sm.sv[p] = w;
+                            if (lds_try && p < HMAX) hash_insert(hkeys, HMASK, w);
                         }
                         const bool is_meet = claimed && dyc[k] != 0u;
                         const int q = wave_append(is_meet, cnt_meet);
                         if (is_meet) meet[q] = w;
                         add[k] = (k == 0 || e + k * TEAM < tot) && dxc[k] == code_new;
                     }
-                    // sigma(w) += sigma(owner) for every arc into the new level:
-                    // all low-word adds first, then the carries into the high words
+                };
+                // sigma(w) += sigma(owner) for every arc into the new level, in
+                // global memory: all low-word adds first, then the carries
+                auto global_adds = [&](const int32_t (&wv)[ARCS], const int32_t (&ow)[ARCS],
+                                       const bool (&add)[ARCS]) {
                     uint64_t olo[ARCS];
 #pragma unroll
                     for (int k = 0; k < ARCS; ++k) olo[k] = 0u;
@@ -768,6 +822,24 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                         const Sigma m = sm.cm[ow[k]];
                         const uint64_t hi = m.hi + ((olo[k] + m.lo) < olo[k] ? 1u : 0u);
                         if (hi) wg_add_u64(&sigx[wv[k]].hi, hi);
+                    }
+                };
+                int32_t wv[ARCS], ow[ARCS];
+                bool add[ARCS];
+#pragma unroll
+                for (int k = 0; k < ARCS; ++k) add[k] = false;
+                for (int32_t e = lane; e < tot; e += ARCS * TEAM) {
+                    claim_round(e, wv, ow, add);
+                    if (!lds_try) global_adds(wv, ow, add);  // else: one round, added below
+                }
+                if (lds_try) {
+                    __syncthreads();  // the claims are done and the set is filled
+                    if (uniform_i32(*cnt_new) <= HMAX) {
+#pragma unroll
+                        for (int k = 0; k < ARCS; ++k)
+                            if (add[k]) lds_add128(&sm.sw[hash_find(hkeys, HMASK, wv[k])], sm.cm[ow[k]]);
+                    } else {
+                        global_adds(wv, ow, add);
                     }
                 }
                 __syncthreads();
@@ -782,6 +854,23 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 sm.nmeet[lp ^ 1] = 0;
             }
             lp ^= 1;
+            // LDS-summed sigma: each new vertex's count to its global slot (at
+            // most two per lane), kept in registers for the bookkeeping below
+            const bool lds_sig = lds_try && nN <= HMAX;
+            Sigma lm0{0u, 0u}, lm1{0u, 0u};
+            if (lds_sig) {
+                if (lane < nN) {
+                    const int32_t w = sm.sv[lane];
+                    lm0 = sm.sw[hash_find(hkeys, HMASK, w)];
+                    sigx[w] = lm0;
+                }
+                if (lane + TEAM < nN) {
+                    const int32_t w = sm.sv[lane + TEAM];
+                    lm1 = sm.sw[hash_find(hkeys, HMASK, w)];
+                    sigx[w] = lm1;
+                }
+                __syncthreads();  // counts stored, set read: the cache may be rewritten
+            }
             if (probe && nM == 0) {  // no meeting on this level: expand it in full
                 retry = true;
                 continue;
@@ -832,8 +921,9 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 const int32_t w2 = two ? (staged_new ? sm.sv[k2] : ballx[base_new + k2]) : w;
                 const int32_t rs = row_ptr[w], re = row_ptr[w + 1];
                 const int32_t rs2 = row_ptr[w2], re2 = row_ptr[w2 + 1];
-                const Sigma m = sigx[w];
-                const Sigma m2 = sigx[w2];
+                // (an LDS-summed level has nN <= 2 TEAM: k = lane, k2 = lane + TEAM)
+                const Sigma m = lds_sig ? lm0 : sigx[w];
+                const Sigma m2 = lds_sig ? lm1 : sigx[w2];
                 const int32_t dg = re - rs;
                 ds += (uint64_t)dg;
                 ms += to128(m);
