@@ -421,15 +421,25 @@ struct SampleShared {
 typedef const __attribute__((address_space(1))) int32_t gint32_t;
 __device__ __forceinline__ gint32_t *as_global(const int32_t *p) { return (gint32_t *)p; }
 
-// lower bound of `key` in the sorted row col[0, len): true if present
-__device__ __forceinline__ bool row_contains(gint32_t *row, int32_t len, int32_t key)
+// true if key is in the sorted row[0, len): a 64-way search by the lanes of
+// one wavefront (row, len and key the same in all of them).  Each round every
+// lane loads the last entry of its segment and a ballot picks the first
+// segment that can hold key, so a row of up to 4096 entries takes two
+// dependent loads.  lw: the lane's index in its wavefront.
+__device__ __forceinline__ bool wave_row_contains(gint32_t *row, int32_t len, int32_t key, int lw)
 {
     int32_t lo = 0, hi = len;
-    while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (row[mid] < key) lo = mid + 1; else hi = mid;
+    while (hi - lo > 64) {
+        const int32_t seg = (hi - lo + 63) >> 6;
+        const int32_t beg = lo + lw * seg;
+        const int32_t end = min(beg + seg, hi);
+        const int32_t last = (beg < hi) ? row[end - 1] : INT32_MAX;  // an empty segment never holds it
+        const uint64_t ge = __ballot(last >= key);
+        if (ge == 0) return false;  // key is above every entry
+        lo += (__ffsll((unsigned long long)ge) - 1) * seg;
+        hi = min(lo + seg, hi);
     }
-    return lo < len && row[lo] == key;
+    return __ballot(lw < hi - lo && row[lo + lw] == key) != 0;
 }
 
 // Among staged (id, weight) pairs sv/sw[0, cnt), the lane holding the
@@ -1087,19 +1097,22 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     __syncthreads();
                     bool done = false;
                     if ((int64_t)(lhi - llo) * 24 < (int64_t)deg) {
-                        // short level, long row: test each level vertex p for
-                        // adjacency to x by a binary search in the shorter of the
-                        // two sorted rows (the graph is symmetric); stage the
-                        // candidates with their counts
-                        for (int32_t k = llo + lane; k < lhi; k += TEAM) {
-                            const int32_t p = balls[k];
+                        // short level, long row: each wavefront takes level
+                        // vertices p in turn and tests p for adjacency to x by a
+                        // 64-way search in the shorter of the two sorted rows (the
+                        // graph is symmetric); stage the candidates with their counts
+                        const int wid = uniform_i32(lane >> 6), lw = lane & 63;
+                        for (int32_t k = llo + wid; k < lhi; k += T::WAVES) {
+                            const int32_t p = uniform_i32(balls[k]);
                             const int32_t prs = row_ptr[p], pdeg = row_ptr[p + 1] - prs;
-                            const bool hit = (pdeg < deg) ? row_contains(col + prs, pdeg, x)
-                                                          : row_contains(col + rs, deg, p);
-                            const int at = wave_append(hit, &sm.ncand);
-                            if (hit && at < STAGE) {
-                                sm.sv[at] = p;
-                                sm.sw[at] = sg[p];
+                            const bool hit = (pdeg < deg) ? wave_row_contains(col + prs, pdeg, x, lw)
+                                                          : wave_row_contains(col + rs, deg, p, lw);
+                            if (hit && lw == 0) {
+                                const int at = atomicAdd(&sm.ncand, 1);
+                                if (at < STAGE) {
+                                    sm.sv[at] = p;
+                                    sm.sw[at] = sg[p];
+                                }
                             }
                         }
                         __syncthreads();
