@@ -309,9 +309,12 @@ def bench_serve(args) -> int:
     {0.05, 0.01}, delta 0.1, checks every 16384 samples) against resident
     graphs.  Two servers answer the same stream: one that runs a query at a
     time (max_active 1, first come first served) and the continuous-batching
-    one.  Each first takes the whole stream at once (saturation: its
-    capacity), then Poisson arrivals at 0.5, 0.8 and 1.0 times the one-at-a-
-    time capacity.  value = the batching server's samples/s at saturation."""
+    one; with --balanced-steps > 0 also a continuous-batching server whose
+    queries use balanced per-vertex delta_L, delta_U (fewer samples per query,
+    so its figures to compare are queries/s and latency).  Each first takes
+    the whole stream at once (saturation: its capacity), then Poisson arrivals
+    at 0.5, 0.8 and 1.0 times the one-at-a-time capacity.  value = the
+    (uniform) batching server's samples/s at saturation."""
     import torch
 
     from paper_1903_09422_amd import Graph, Server, graphs
@@ -334,27 +337,33 @@ def bench_serve(args) -> int:
             if off > now:
                 time.sleep(off - now)
             tickets.append((srv.submit(gi, eps, delta, seed, n_check), time.perf_counter() - t0))
-        tot, end = 0, 0.0
+        tot, first, end = 0, 0, 0.0
         for (t, ts), (gi, *_rest) in zip(tickets, queries):
             srv.wait(t)
             res, lat = srv.result(t, gi, scores=False)
             tot += res.tau
+            first += res.stats["first_samples"]
             end = max(end, ts + lat / 1e3)
             srv.release(t)
-        return tot, end, srv.info()
+        info = srv.info()
+        info["first_samples"] = first
+        return tot, end, info
 
     out_rates = {}
     legs = {}
-    for name, max_active in (("one_at_a_time", 1), ("batching", 0)):
+    servers = [("one_at_a_time", 1, 0), ("batching", 0, 0)]
+    if args.balanced_steps > 0:
+        servers.append(("batching_balanced", 0, 1))
+    for name, max_active, balance in servers:
         srv = Server(handles, max_active=max_active)
         for k, v in (("team", args.team), ("slots", args.slots), ("probe_min", args.probe_min),
-                     ("epochs_per_launch", args.epochs_per_launch)):
+                     ("epochs_per_launch", args.epochs_per_launch), ("balance", balance)):
             srv.set_param(k, v)
         replay(srv, None)  # warm-up: pool, buffers, code
         torch.cuda.synchronize()
         tot, span, info = replay(srv, None)
         legs[name] = {"samples_per_s": tot / span, "queries_per_s": len(queries) / span,
-                      "makespan_s": span, "samples": tot,
+                      "makespan_s": span, "samples": tot, "first_phase_samples": info["first_samples"],
                       "p50_ms": info["p50_ms"], "p99_ms": info["p99_ms"],
                       "peak_active": info["peak_active"]}
         print(f"serve: {name} saturated {tot / span:.4g} samples/s", file=sys.stderr, flush=True)
