@@ -271,6 +271,21 @@ def bench_batch(args) -> int:
         lat.append((time.perf_counter() - ts) * 1e3)
     t_batch = time.perf_counter() - t0
     assert s_serial == s_batch
+    balanced = None
+    if args.balanced_steps > 0:
+        # the same batch with balanced per-vertex delta_L, delta_U: time per batch
+        batch.set_param("balance", 1)
+        batched()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            s_bal = batched()
+        t_bal = (time.perf_counter() - t0) / args.steps
+        first = sum(batch.stats(k)["first_samples"] for k in range(len(pool)))
+        batch.set_param("balance", 0)
+        balanced = {"ms_per_batch": t_bal * 1e3, "uniform_ms_per_batch": t_batch * 1e3 / args.steps,
+                    "speedup": (t_batch / args.steps) / t_bal, "samples": s_bal,
+                    "first_phase_samples": first, "uniform_samples": s_batch // args.steps}
     out = {
         "metric": "samples/s (KADABRA adaptive sampling, 64-query batch)",
         "value": s_batch / t_batch,
@@ -296,6 +311,8 @@ def bench_batch(args) -> int:
         "speedup_vs_serial": (s_batch / t_batch) / (s_serial / t_serial),
         "batch_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
     }
+    if balanced:
+        out["balanced"] = balanced
     batch.close()
     for h in handles:
         h.close()

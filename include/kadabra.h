@@ -229,9 +229,10 @@ typedef struct kadabra_batch kadabra_batch;
 /* Creates an empty batch on the current device.  Errors: ENOMEM, EDEVICE. */
 int kadabra_batch_create(kadabra_batch **out);
 
-/* As kadabra_set_param for the batch's mapping ("team", "slots", "frames",
- * "overlap", "probe_min", "test_fail_alloc", "test_level_cap"); "check_interval" is per
- * query. */
+/* As kadabra_set_param for the batch ("team", "slots", "frames", "overlap",
+ * "epochs_per_launch", "probe_min", "balance", "balance_samples" and the test
+ * hooks); each applies to every query at the next kadabra_batch_run.
+ * "check_interval" is per query. */
 int kadabra_batch_set_param(kadabra_batch *b, const char *key, int64_t value);
 int kadabra_batch_get_param(const kadabra_batch *b, const char *key, int64_t *value);
 int kadabra_batch_set_stream(kadabra_batch *b, void *hip_stream);
@@ -294,8 +295,9 @@ typedef struct {
  * meanwhile; their own runs stay independent).  hbm_budget_bytes bounds the
  * device memory of admitted queries (per query: counters 4n, score buffer
  * 8n, and while sampling the frame sets 8n * frames * epochs_per_launch
- * bytes); 0 takes half of the device memory free after the sample pool is
- * sized.  max_active bounds the queries in one launch (0: 256).
+ * bytes, plus with "balance" the first-phase counters 4n and the plan tables
+ * 20 (M1 + 1) bytes); 0 takes half of the device memory free after the
+ * sample pool is sized.  max_active bounds the queries in one launch (0: 256).
  * Errors: EINVAL, ENOMEM, EDEVICE.
  */
 int kadabra_server_create(const kadabra_graph *const *graphs, int32_t ngraphs, int64_t hbm_budget_bytes,

@@ -1126,6 +1126,12 @@ struct kadabra_server {
 
 namespace {
 
+// First-phase samples of a query with cap omega under p (0: uniform constants).
+int64_t first_phase_of(const Params &p, int64_t omega)
+{
+    return p.balance ? (p.balance_samples ? p.balance_samples : (omega + 19) / 20) : 0;
+}
+
 int make_query(Query &q, const GraphData &gd, const Params &p, double eps, double delta, uint64_t seed,
                int64_t N)
 {
@@ -1146,7 +1152,7 @@ int make_query(Query &q, const GraphData &gd, const Params &p, double eps, doubl
     q.probe_min = p.probe_min;
     q.omega = omega;
     q.L = std::log(4.0 * (double)gd.n / delta);
-    q.m1 = p.balance ? (p.balance_samples ? p.balance_samples : (omega + 19) / 20) : 0;
+    q.m1 = first_phase_of(p, omega);
     q.t_submit = std::chrono::steady_clock::now();
     return KADABRA_OK;
 }
@@ -1663,6 +1669,7 @@ int kadabra_batch_run(kadabra_batch *b)
         q->epl = b->params.epochs;
         q->nsets = 2 * b->params.epochs;
         q->probe_min = b->params.probe_min;
+        q->m1 = first_phase_of(b->params, q->omega);
         qs.push_back(q.get());
     }
     OK_OR_RETURN(run_queries(b->runner, qs, b->params));

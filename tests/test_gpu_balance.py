@@ -156,6 +156,19 @@ def test_balanced_batch_and_server():
             assert got.tau == w.tau and np.array_equal(got.counts, w.counts)
             assert got.stats["plan_tau"] == w.stats["plan_tau"]
             assert got.stats["first_e_scan"] == w.stats["first_e_scan"]
+        # the parameter applies to the queries already added, at the next run
+        b.set_param("balance", 0)
+        b.run()
+        for k, ((g, eps, n_check), seed) in enumerate(items):
+            got = b.result(k)
+            u = oracle.run(g, eps, 0.1, seed, n_check)
+            assert got.tau == u.tau and np.array_equal(got.counts, u.counts)
+            assert got.stats["first_samples"] == 0
+        b.set_param("balance", 1)
+        b.run()
+        for k, w in enumerate(want):
+            got = b.result(k)
+            assert got.tau == w.tau and np.array_equal(got.counts, w.counts)
     print("case balanced server", flush=True)
     with Server(handles) as srv:
         srv.set_param("balance", 1)
