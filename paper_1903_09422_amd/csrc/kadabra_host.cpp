@@ -771,6 +771,9 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
             // callers pass only queries with samples left
             int64_t epoch = q.k, hi = q.lo;
             for (int j = 0; j < epochs_now && hi < q.omega && (sample_cap < 0 || hi < sample_cap); ++j) {
+                // the interval cut short by omega is never joined to earlier ones:
+                // it is reached only if every earlier check fails
+                if (j > 0 && sample_cap < 0 && (epoch + 1) * q.N > q.omega) break;
                 ++epoch;
                 hi = q.bound(epoch);
                 if (sample_cap >= 0) hi = std::min(hi, sample_cap);
