@@ -76,6 +76,34 @@ def test_check_intervals_and_ragged_last_epoch(n_check):
         assert_same(got, want)
 
 
+def _double_star(a, b):
+    """Centers 0 and 1 adjacent; a leaves on 0, b leaves on 1."""
+    u = [0] + [0] * a + [1] * b
+    v = [1] + list(range(2, 2 + a)) + list(range(2 + a, 2 + a + b))
+    return G.from_edges(2 + a + b, np.array(u), np.array(v), name=f"dstar{a}_{b}")
+
+
+@pytest.mark.parametrize("team", [64, 256])
+@pytest.mark.parametrize("probe", [-1, 1 << 40])
+def test_level_sigma_paths(team, probe):
+    """Levels whose sigma is summed in LDS (one-chunk frontier, one round of
+    arcs, at most STAGE/2 new vertices), levels that fall back to global adds
+    after the claims (a center's expansion with the probe off: a new level of
+    up to 1500 leaves in one round), and multi-chunk levels (a grid's wide
+    rings), with the meeting probe on (auto) and off."""
+    # double stars: with the probe off, the smaller center is expanded in
+    # full: 1000 or 600 new vertices (beyond STAGE/2 for any team: global adds)
+    # or 300 (LDS for 256-lane teams)
+    cases = [(_double_star(1500, 1000), 0.1, 100), (_double_star(700, 600), 0.1, 100),
+             (_double_star(400, 300), 0.1, 64), (G.grid_graph(40, 40), 0.05, 200),
+             (G.complete_bipartite(3, 700), 0.1, 50)]
+    for g, eps, n_check in cases:
+        print(f"case {g.name} team={team} probe_min={probe}", flush=True)
+        for seed in (2, 3):
+            want = oracle.run(g, eps, 0.1, seed, n_check)
+            assert_same(gpu_run(g, eps, 0.1, seed, n_check, team=team, probe_min=probe), want)
+
+
 def test_layered_graph_with_huge_sigma():
     # 17^(d-1) shortest paths: sigma beyond 2^104 forces level rescaling
     width, layers = 17, 80
