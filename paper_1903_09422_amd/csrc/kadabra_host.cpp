@@ -9,13 +9,18 @@
 //   Runner      the device engine: a pool of sample slots shared by all
 //               queries, a control block per query, and the round loop.  In a
 //               round the stream runs
-//                 sample_kernel   the next epoch [B_{k-1}, B_k) of every active query
-//                 merge_check     counters += frames; stopping rule on [0, B_k)
+//                 sample_kernel   the next epochs (up to epochs_per_launch
+//                                 check intervals) of every active query
+//                 merge_check     per boundary B_k in order: counters +=
+//                                 frames, stopping rule on [0, B_k)
 //                 copy            every query's control block to the host
-//               and, with overlap on, the following epoch's samples are queued
+//               and, with overlap on, the following epochs' samples are queued
 //               before the host reads the flags; a query that stopped makes
 //               them exit on the device (the counters checked at B_k hold
-//               exactly samples [0, B_k) either way).
+//               exactly samples [0, B_k) either way).  A query with balanced
+//               delta_L(v), delta_U(v) also carries its first phase in its
+//               first launch, followed by the histogram and plan kernels
+//               (kadabra_balance.hip) before its first check.
 //   kadabra_graph   one graph on the device, running one query at a time.
 //   kadabra_batch   many queries on many graphs in the same launches.
 //   kadabra_server  continuous batching: a worker thread runs the round loop

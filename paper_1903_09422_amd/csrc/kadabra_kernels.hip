@@ -2,11 +2,12 @@
 //
 //   sample_kernel      one team (one to eight wavefronts) per sample in flight;
 //                      persistent over the sample indices of the launch (one or
-//                      more epochs of each query), claimed from a counter.  Per sample: pair draw,
+//                      more epochs of each query, and a balanced query's first
+//                      phase), claimed from a counter.  Per sample: pair draw,
 //                      same-component test, balanced bidirectional BFS with
-//                      128-bit path counts, meeting-vertex draw, backtracking
-//                      on CSR + distances, +1 on the interior vertices
-//                      (Section 2.3, Appendix C.1).
+//                      128-bit path counts (small levels summed in LDS), the
+//                      meeting-vertex draw, backtracking on CSR + distances,
+//                      +1 on the interior vertices (Section 2.3, Appendix C.1).
 //   merge_check_kernel counters += frames of the epoch (frames zeroed), then
 //                      the FP64 stopping rule f, g <= eps of Appendix B for
 //                      every vertex (uniform or per-vertex constants); one
