@@ -743,10 +743,10 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
             Query &q = *qs[x];
             int epochs_now = q.epl;
             if (q.m1 > 0 && !q.first_launched && !speculative && sample_cap < 0) {
-                // a balanced run is planned to stop early: its first launch
-                // carries one check interval, so that the first check comes
-                // as soon as possible
-                // the first phase: its samples are claimed first and add into c1
+                // a balanced query's first launch: the first phase, claimed
+                // first and added into c1, then one check interval only (the
+                // run is planned to stop early, so its first check should
+                // come as soon as possible)
                 kd::QueryDesc &d = h[nd++];
                 d = kd::QueryDesc{};
                 d.row_ptr = q.gd->d_row_ptr;
