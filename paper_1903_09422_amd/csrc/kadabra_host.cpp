@@ -267,6 +267,10 @@ int get_common_param(const Params &p, const char *key, int64_t *value)
 }
 
 // A graph resident on the device, plus what depends on the graph only.
+// On a high-diameter graph the device arrays use an internal vertex order
+// (relabel_for_locality); d_perm maps original to internal ids, d_iperm back,
+// and d_colo holds each internal row's neighbours as original ids (the row
+// order is the original one, ascending in original id).  Null: identity.
 struct GraphData {
     int32_t n = 0;
     int64_t arcs = 0;
@@ -274,11 +278,16 @@ struct GraphData {
     int32_t vd = 1;
     int32_t ncomp = 0;
     int32_t *d_row_ptr = nullptr, *d_col = nullptr, *d_comp = nullptr;
+    int32_t *d_colo = nullptr, *d_perm = nullptr, *d_iperm = nullptr;
+    std::vector<int32_t> h_perm;  // host copy of d_perm (empty: identity)
     ~GraphData()
     {
         dev_free(d_row_ptr);
         dev_free(d_col);
         dev_free(d_comp);
+        dev_free(d_colo);
+        dev_free(d_perm);
+        dev_free(d_iperm);
     }
 };
 
@@ -752,6 +761,9 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
                 d.row_ptr = q.gd->d_row_ptr;
                 d.col = q.gd->d_col;
                 d.comp = q.gd->d_comp;
+                d.perm = q.gd->d_perm;
+                d.iperm = q.gd->d_iperm;
+                d.colo = q.gd->d_colo;
                 d.frames = q.c1;
                 d.ctl = d_ctl + q.cslot;
                 d.seed = q.seed;
@@ -789,6 +801,9 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
             d.row_ptr = q.gd->d_row_ptr;
             d.col = q.gd->d_col;
             d.comp = q.gd->d_comp;
+            d.perm = q.gd->d_perm;
+            d.iperm = q.gd->d_iperm;
+            d.colo = q.gd->d_colo;
             d.frames = q.frames;
             d.ctl = d_ctl + q.cslot;
             d.seed = q.seed;
@@ -824,7 +839,9 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
         L.e1 = take_event();
         if (!L.e0 || !L.e1) return fail(KADABRA_EDEVICE, "event creation failed");
         HIP_OR_FAIL(hipEventRecord(L.e0, stream));
-        HIP_OR_FAIL(kd::launch_sample(team, (int)slots, sa, stream));
+        bool mapped = false;
+        for (Query *q : qs) mapped = mapped || q->gd->d_perm != nullptr;
+        HIP_OR_FAIL(kd::launch_sample(team, (int)slots, sa, mapped, stream));
         HIP_OR_FAIL(hipEventRecord(L.e1, stream));
         pend.push_back(std::move(L));
         // the balanced constants, from the finished first phase, before any check
@@ -872,6 +889,7 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
                 m.set = q.set_of(epoch);
                 m.frames = q.frames + (size_t)m.set * q.nframes * (size_t)q.gd->n;
                 m.ctl = d_ctl + q.cslot;
+                m.perm = q.gd->d_perm;
                 m.c1 = q.first_launched ? q.c1 : nullptr;
                 m.lcon = q.first_launched ? q.lcon() : nullptr;
                 m.m1 = q.first_launched ? q.m1 : 0;
@@ -1397,6 +1415,129 @@ const char *kadabra_last_error(void) { return g_last_error.c_str(); }
 
 int kadabra_version(void) { return 10100; }
 
+// Graphs whose vertex-diameter bound reaches this are relabelled for locality.
+constexpr int32_t kRelabelMinVd = 64;
+
+// Reverse Cuthill-McKee order: per component (in order of its smallest id), a
+// BFS from a pseudo-peripheral vertex (of the deepest level of a BFS from the
+// component's smallest id, the one of least degree, lowest id on ties) that
+// queues each vertex's unplaced neighbours by (degree, id); the whole order is
+// then reversed.  Returns order[k] = the original id of internal vertex k.
+std::vector<int32_t> rcm_order(int32_t n, const int32_t *rp, const int32_t *col)
+{
+    auto deg = [&](int32_t v) { return rp[v + 1] - rp[v]; };
+    std::vector<int32_t> order, q, nb;
+    order.reserve((size_t)n);
+    q.reserve((size_t)n);
+    std::vector<int32_t> dist((size_t)n, -1);
+    std::vector<char> placed((size_t)n, 0);
+    for (int32_t seed = 0; seed < n; ++seed) {
+        if (placed[(size_t)seed]) continue;
+        q.clear();
+        q.push_back(seed);
+        dist[(size_t)seed] = 0;
+        for (size_t h = 0; h < q.size(); ++h) {
+            const int32_t u = q[h];
+            for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+                const int32_t w = col[e];
+                if (dist[(size_t)w] < 0) {
+                    dist[(size_t)w] = dist[(size_t)u] + 1;
+                    q.push_back(w);
+                }
+            }
+        }
+        const int32_t dmax = dist[(size_t)q.back()];
+        int32_t start = -1;
+        for (int32_t v : q)
+            if (dist[(size_t)v] == dmax &&
+                (start < 0 || deg(v) < deg(start) || (deg(v) == deg(start) && v < start)))
+                start = v;
+        for (int32_t v : q) dist[(size_t)v] = -1;
+        const size_t base = order.size();
+        order.push_back(start);
+        placed[(size_t)start] = 1;
+        for (size_t h = base; h < order.size(); ++h) {
+            const int32_t u = order[h];
+            nb.clear();
+            for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+                const int32_t w = col[e];
+                if (!placed[(size_t)w]) {
+                    placed[(size_t)w] = 1;
+                    nb.push_back(w);
+                }
+            }
+            std::sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) {
+                return deg(a) != deg(b) ? deg(a) < deg(b) : a < b;
+            });
+            order.insert(order.end(), nb.begin(), nb.end());
+        }
+    }
+    std::reverse(order.begin(), order.end());
+    return order;
+}
+
+// Replaces the device graph by its internal order (a layout change only:
+// every result is the one of the original order, see GraphData).  BFS balls
+// of a high-diameter graph then fall in fewer cache lines.
+int relabel_for_locality(GraphData &gd, const int32_t *row_ptr, const int32_t *col, hipStream_t s)
+{
+    const int32_t n = gd.n;
+    const size_t m = (size_t)gd.arcs;
+    std::vector<int32_t> iperm = rcm_order(n, row_ptr, col);
+    std::vector<int32_t> perm((size_t)n);
+    for (int32_t k = 0; k < n; ++k) perm[(size_t)iperm[(size_t)k]] = k;
+    std::vector<int32_t> rp2((size_t)n + 1), col2(m), colo(m);
+    rp2[0] = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const int32_t o = iperm[(size_t)k];
+        const int32_t d = row_ptr[o + 1] - row_ptr[o];
+        rp2[(size_t)k + 1] = rp2[(size_t)k] + d;
+        for (int32_t j = 0; j < d; ++j) {
+            const int32_t w = col[row_ptr[o] + j];
+            col2[(size_t)rp2[(size_t)k] + j] = perm[(size_t)w];
+            colo[(size_t)rp2[(size_t)k] + j] = w;
+        }
+    }
+    int32_t *d_rp = nullptr, *d_c = nullptr, *d_co = nullptr, *d_p = nullptr, *d_ip = nullptr, *d_comp = nullptr;
+    auto drop = [&] {
+        dev_free(d_rp);
+        dev_free(d_c);
+        dev_free(d_co);
+        dev_free(d_p);
+        dev_free(d_ip);
+        dev_free(d_comp);
+    };
+    hipError_t e = hipSuccess;
+    if ((e = alloc_n(&d_rp, (size_t)n + 1)) != hipSuccess || (e = alloc_n(&d_c, m)) != hipSuccess ||
+        (e = alloc_n(&d_co, m)) != hipSuccess || (e = alloc_n(&d_p, (size_t)n)) != hipSuccess ||
+        (e = alloc_n(&d_ip, (size_t)n)) != hipSuccess || (e = alloc_n(&d_comp, (size_t)n)) != hipSuccess) {
+        drop();
+        return fail(e == hipErrorOutOfMemory ? KADABRA_ENOMEM : KADABRA_EDEVICE, "relabelling: %s",
+                    hipGetErrorString(e));
+    }
+    if ((e = hipMemcpy(d_rp, rp2.data(), ((size_t)n + 1) * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+        (m && (e = hipMemcpy(d_c, col2.data(), m * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess) ||
+        (m && (e = hipMemcpy(d_co, colo.data(), m * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess) ||
+        (e = hipMemcpy(d_p, perm.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d_ip, iperm.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = kd::launch_gather_i32(d_comp, gd.d_comp, d_ip, n, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess) {
+        drop();
+        return fail(KADABRA_EDEVICE, "relabelling: %s", hipGetErrorString(e));
+    }
+    dev_free(gd.d_row_ptr);
+    dev_free(gd.d_col);
+    dev_free(gd.d_comp);
+    gd.d_row_ptr = d_rp;
+    gd.d_col = d_c;
+    gd.d_colo = d_co;
+    gd.d_perm = d_p;
+    gd.d_iperm = d_ip;
+    gd.d_comp = d_comp;
+    gd.h_perm = std::move(perm);
+    return KADABRA_OK;
+}
+
 int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr, const int32_t *col_idx,
                          kadabra_graph **out)
 {
@@ -1424,6 +1565,7 @@ int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr, co
     // the graph is read by kernels on non-blocking streams: the uploads land first
     HIP_OR_FAIL(hipDeviceSynchronize());
     OK_OR_RETURN(gpu_preprocess(gd, g->runner.own_stream));
+    if (gd.vd >= kRelabelMinVd) OK_OR_RETURN(relabel_for_locality(gd, row_ptr, col_idx, g->runner.own_stream));
     *out = g.release();
     return KADABRA_OK;
 }
@@ -1445,6 +1587,7 @@ int kadabra_get_param(const kadabra_graph *g, const char *key, int64_t *value)
     if (!strcmp(key, "vd_bound")) *value = g->gd.vd;
     else if (!strcmp(key, "components")) *value = g->gd.ncomp;
     else if (!strcmp(key, "max_degree")) *value = g->gd.max_deg;
+    else if (!strcmp(key, "relabeled")) *value = g->gd.d_perm ? 1 : 0;
     else if (!strcmp(key, "last_team")) *value = g->runner.team;
     else if (!strcmp(key, "last_slots")) *value = g->runner.slots;
     else return fail(KADABRA_EINVAL, "unknown parameter '%s'", key);
@@ -1539,12 +1682,14 @@ int kadabra_get_balance(const kadabra_graph *g, double *log_inv_delta_L, double 
     HIP_OR_FAIL(hipMemcpyAsync(lcon.data(), q.lcon(), lcon.size() * sizeof(double), hipMemcpyDeviceToHost,
                                g->runner.stream));
     HIP_OR_FAIL(hipStreamSynchronize(g->runner.stream));
+    const std::vector<int32_t> &perm = g->gd.h_perm;  // c1 is in the internal order
     for (size_t v = 0; v < n; ++v) {
-        const size_t k = (size_t)c1[v];
+        const int32_t c = c1[perm.empty() ? v : (size_t)perm[v]];
+        const size_t k = (size_t)c;
         if (k > (size_t)q.m1) return fail(KADABRA_EDEVICE, "first-phase counter out of range");
         if (log_inv_delta_L) log_inv_delta_L[v] = lcon[2 * k];
         if (log_inv_delta_U) log_inv_delta_U[v] = lcon[2 * k + 1];
-        if (first_counts) first_counts[v] = c1[v];
+        if (first_counts) first_counts[v] = c;
     }
     return KADABRA_OK;
 }

@@ -67,6 +67,9 @@ struct QueryDesc {
     const int32_t *row_ptr;
     const int32_t *col;
     const int32_t *comp;
+    const int32_t *perm;   // original -> internal vertex id (null: the same)
+    const int32_t *iperm;  // internal -> original
+    const int32_t *colo;   // col as original ids (rows ascending in them)
     int32_t *frames;      // every frame set: [nsets][nframes][n]
     Control *ctl;
     uint64_t seed;
@@ -103,6 +106,8 @@ struct MergeDesc {
     int32_t *counts;      // [n] counters of samples [0, tau)
     int32_t *frames;      // the epoch's frame set: [nframes][n]
     Control *ctl;
+    const int32_t *perm;  // counters are in the original order, frames and c1 in the
+                          // internal one: vertex v's entries are at perm[v] (null: v)
     const int32_t *c1;    // balanced runs: first-phase counters [n]; the vertex's constants
     const double *lcon;   // are lcon[2 c1[v]] (delta_L) and lcon[2 c1[v] + 1] (delta_U);
                           // null: L for every vertex
@@ -138,7 +143,8 @@ struct PlanArgs {
     int32_t cache_rows;   // test hook: > 0 caps the histogram rows the search keeps in LDS
 };
 
-hipError_t launch_sample(int team, int slots, const SampleArgs &a, hipStream_t s);
+// mapped: some query of the launch is on a relabelled graph
+hipError_t launch_sample(int team, int slots, const SampleArgs &a, bool mapped, hipStream_t s);
 hipError_t launch_hist(const int32_t *c1, int32_t n, int32_t *hist, int64_t m1, Control *ctl, hipStream_t s);
 hipError_t launch_plan(const PlanArgs &a, hipStream_t s);
 hipError_t launch_merge_check(const MergeArgs &a, hipStream_t s);
@@ -159,6 +165,7 @@ hipError_t launch_bfs_roots(const int32_t *row_ptr, const int32_t *comp, int32_t
 hipError_t launch_bfs_level(const int32_t *row_ptr, const int32_t *col, const int32_t *frontier,
                             const int32_t *count, int32_t frontier_size, int32_t level, int32_t *dist,
                             int32_t *next, int32_t *next_count, hipStream_t s);
+hipError_t launch_gather_i32(int32_t *dst, const int32_t *src, const int32_t *idx, int32_t n, hipStream_t s);
 hipError_t launch_bfs_small(const int32_t *row_ptr, const int32_t *col, int32_t *dist, int32_t *q0, int32_t *q1,
                             int32_t *state, int32_t small_max, hipStream_t s);
 

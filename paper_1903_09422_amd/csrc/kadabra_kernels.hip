@@ -506,7 +506,9 @@ __device__ __forceinline__ void clear_ball(const int32_t *ball, int32_t len, uin
 
 // Wave/workgroup-per-sample sampler.  Every lane of the team runs the same
 // control flow; per-sample scalars live in registers (uniform) or LDS.
-template <int TEAM>
+// MAPPED: some query of the launch is on a relabelled graph (its descriptor
+// has the vertex maps); without it the maps are never read.
+template <int TEAM, bool MAPPED>
 __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void sample_kernel(SampleArgs a)
 {
     using T = Team<TEAM>;
@@ -612,9 +614,18 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
         // -- pair: ordered, s != t, uniform (64-bit multiply-high mapping) --
         uint64_t u_t;
         const uint64_t u_s = philox_u64(seed, (uint64_t)i, 0u, &u_t);
-        const int32_t s = (int32_t)__umul64hi(u_s, (uint64_t)nv);
+        int32_t s = (int32_t)__umul64hi(u_s, (uint64_t)nv);
         int32_t t = (int32_t)__umul64hi(u_t, (uint64_t)(nv - 1));
         t += (t >= s) ? 1 : 0;
+        // a relabelled graph: ids below are internal; ties are still broken
+        // by original id (meeting draw, level-list candidates).  The maps are
+        // read from the descriptor where used, not held through the search.
+        if (MAPPED) {
+            const int32_t *const pm = qd->perm;
+            const int32_t ms = pm ? pm[s] : s, mt = pm ? pm[t] : t;
+            s = uniform_i32(ms);
+            t = uniform_i32(mt);
+        }
         // the component test and both rows' bounds, loaded together
         const int32_t cs = comp[s], ct = comp[t];
         const int32_t rs_s = row_ptr[s], re_s = row_ptr[s + 1];
@@ -979,17 +990,18 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 // one meeting vertex per lane: its product stays in registers
                 // between the maximum and the weight
                 const bool has = lane < nM;
-                int32_t w = 0;
+                int32_t w = 0, wo = 0;  // internal and original id
                 U256 p{0, 0};
                 if (has) {
                     w = meet_staged ? sm.sv[lane] : meet[lane];
+                    wo = (MAPPED && qd->iperm) ? qd->iperm[w] : w;
                     p = mul_128x128(to128(sig0[w]), to128(sig1[w]));
                 }
                 const U256 pm = T::max_u256(p, redA);
                 const int shp = max(0, bitw256(pm) - WEIGHT_BITS);
                 const uint64_t wt = has ? ceil_shr256(p, shp) : 0u;
                 if (has) {
-                    sm.sv[lane] = w;
+                    sm.sv[lane] = wo;  // ranked by original id
                     sm.sw[lane] = Sigma{wt, 0u};
                 }
                 const uint64_t tot = T::sum_u64(wt, redB);
@@ -1001,6 +1013,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 pick_by_id_prefix<TEAM>(sm.sv, sm.sw, nM, (u128)r, &sm.pick);
                 __syncthreads();
                 v = uniform_i32(sm.pick);
+                if (MAPPED && qd->perm) v = qd->perm[v];
                 // every wave holds v before backtracking resets sm.pick
                 __syncthreads();
             } else {
@@ -1017,17 +1030,19 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 int32_t vmin = nv, vmax = -1;
                 for (int32_t k = lane; k < nM; k += TEAM) {
                     const int32_t w = meet[k];
+                    const int32_t wo = (MAPPED && qd->iperm) ? qd->iperm[w] : w;  // ranked by original id
                     const uint64_t wt =
                         ceil_shr256(mul_128x128(to128(sig0[w]), to128(sig1[w])), shp);
                     if (staged) {
-                        sm.sv[k] = w;
+                        sm.sv[k] = wo;
                         sm.sw[k] = Sigma{wt, 0u};
                     } else {
+                        meet[k] = wo;
                         meetw[k] = wt;
                     }
                     tot += wt;
-                    vmin = min(vmin, w);
-                    vmax = max(vmax, w);
+                    vmin = min(vmin, wo);
+                    vmax = max(vmax, wo);
                 }
                 tot = T::sum_u64(tot, redB);
                 // team min / max of the ids (as maxima of n - id and id + 1)
@@ -1068,7 +1083,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     part = T::sum_u64(part, (it++ & 1) ? redB : redA);
                     if (part > r) hi = mid; else lo = mid + 1;
                 }
-                v = lo;
+                v = (MAPPED && qd->perm) ? qd->perm[lo] : lo;
             }
             PHASE_MARK(3);
             // v's distances: one more than side X's frontier level, side Y's level
@@ -1096,22 +1111,28 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                         sm.ncand = 0;
                     }
                     __syncthreads();
-                    bool done = false;
+                    bool done = false, probe_pick = false;
                     if ((int64_t)(lhi - llo) * 24 < (int64_t)deg) {
                         // short level, long row: each wavefront takes level
                         // vertices p in turn and tests p for adjacency to x by a
                         // 64-way search in the shorter of the two sorted rows (the
                         // graph is symmetric); stage the candidates with their counts
+                        // (on a relabelled graph the rows are searched in original
+                        // ids, and candidates are ranked by them)
                         const int wid = uniform_i32(lane >> 6), lw = lane & 63;
+                        gint32_t *const colk = (MAPPED && qd->colo) ? as_global(qd->colo) : col;
+                        const int32_t *const iperm = MAPPED ? qd->iperm : nullptr;
+                        const int32_t xo = iperm ? iperm[x] : x;
                         for (int32_t k = llo + wid; k < lhi; k += T::WAVES) {
                             const int32_t p = uniform_i32(balls[k]);
+                            const int32_t po = iperm ? iperm[p] : p;
                             const int32_t prs = row_ptr[p], pdeg = row_ptr[p + 1] - prs;
-                            const bool hit = (pdeg < deg) ? wave_row_contains(col + prs, pdeg, x, lw)
-                                                          : wave_row_contains(col + rs, deg, p, lw);
+                            const bool hit = (pdeg < deg) ? wave_row_contains(colk + prs, pdeg, xo, lw)
+                                                          : wave_row_contains(colk + rs, deg, po, lw);
                             if (hit && lw == 0) {
                                 const int at = atomicAdd(&sm.ncand, 1);
                                 if (at < STAGE) {
-                                    sm.sv[at] = p;
+                                    sm.sv[at] = po;
                                     sm.sw[at] = sg[p];
                                 }
                             }
@@ -1124,7 +1145,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                             const u128 tot = T::sum_u128(part, redA);
                             const u128 r = mulhi_64x128(U, tot);
                             pick_by_id_prefix<TEAM>(sm.sv, sm.sw, nc, r, &sm.pick);
-                            done = true;
+                            done = probe_pick = true;
                         }
                     }
                     if (!done && deg <= TEAM) {
@@ -1184,6 +1205,8 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     __syncthreads();
                     x = uniform_i32(sm.pick);
                     __syncthreads();
+                    // the level-list path picks an original id
+                    if (MAPPED && x >= 0 && probe_pick && qd->perm) x = qd->perm[x];
                     if (x < 0) {  // no predecessor found: cannot happen on a BFS level
                         if (lane == 0 && atomicCAS(&qctl->err, 0, 2) == 0)
                             atomicExch((unsigned long long *)&qctl->err_sample, (unsigned long long)i);
@@ -1267,16 +1290,18 @@ __global__ __launch_bounds__(MERGE_BLOCK) void merge_check_kernel(MergeArgs a)
     const double t = (double)M.tau, w = (double)M.omega;
     int viol = 0;
     for (size_t v = (size_t)qb * MERGE_BLOCK + threadIdx.x; v < n; v += (size_t)nb * MERGE_BLOCK) {
+        // counters in the original vertex order, frames and c1 in the internal one
+        const size_t iv = M.perm ? (size_t)M.perm[v] : v;
         int32_t c = M.counts[v];
         for (int f = 0; f < M.nframes; ++f) {
-            c += M.frames[(size_t)f * n + v];
-            M.frames[(size_t)f * n + v] = 0;
+            c += M.frames[(size_t)f * n + iv];
+            M.frames[(size_t)f * n + iv] = 0;
         }
         M.counts[v] = c;
         if (M.do_check) {
             double LL = M.L, LU = M.L;
             if (M.lcon) {  // balanced: the constants of the vertex's first-phase count
-                int64_t k = M.c1[v];
+                int64_t k = M.c1[iv];
                 k = k < 0 ? 0 : (k > M.m1 ? M.m1 : k);  // in range (else device error 4 is set)
                 LL = M.lcon[2 * k];
                 LU = M.lcon[2 * k + 1];
@@ -1324,19 +1349,25 @@ static unsigned grid_for(size_t count, unsigned block)
     return g ? (unsigned)g : 1u;
 }
 
-hipError_t launch_sample(int team, int slots, const SampleArgs &a, hipStream_t s)
+template <bool MAPPED>
+static hipError_t launch_sample_as(int team, int slots, const SampleArgs &a, hipStream_t s)
 {
     if (team == 64)
-        hipLaunchKernelGGL(sample_kernel<64>, dim3(slots), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((sample_kernel<64, MAPPED>), dim3(slots), dim3(64), 0, s, a);
     else if (team == 128)
-        hipLaunchKernelGGL(sample_kernel<128>, dim3(slots), dim3(128), 0, s, a);
+        hipLaunchKernelGGL((sample_kernel<128, MAPPED>), dim3(slots), dim3(128), 0, s, a);
     else if (team == 256)
-        hipLaunchKernelGGL(sample_kernel<256>, dim3(slots), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((sample_kernel<256, MAPPED>), dim3(slots), dim3(256), 0, s, a);
     else if (team == 512)
-        hipLaunchKernelGGL(sample_kernel<512>, dim3(slots), dim3(512), 0, s, a);
+        hipLaunchKernelGGL((sample_kernel<512, MAPPED>), dim3(slots), dim3(512), 0, s, a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+hipError_t launch_sample(int team, int slots, const SampleArgs &a, bool mapped, hipStream_t s)
+{
+    return mapped ? launch_sample_as<true>(team, slots, a, s) : launch_sample_as<false>(team, slots, a, s);
 }
 
 hipError_t launch_merge_check(const MergeArgs &a, hipStream_t s)

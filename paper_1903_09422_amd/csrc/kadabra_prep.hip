@@ -280,4 +280,20 @@ hipError_t launch_bfs_small(const int32_t *row_ptr, const int32_t *col, int32_t 
     return hipGetLastError();
 }
 
+// dst[i] = src[idx[i]] (a relabelled copy of a per-vertex array)
+__global__ void gather_i32_kernel(int32_t *dst, const int32_t *src, const int32_t *idx, int32_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[idx[i]];
+}
+
+hipError_t launch_gather_i32(int32_t *dst, const int32_t *src, const int32_t *idx, int32_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    size_t g = ((size_t)n + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(gather_i32_kernel, dim3((unsigned)g), dim3(256), 0, s, dst, src, idx, n);
+    return hipGetLastError();
+}
+
 }  // namespace kd

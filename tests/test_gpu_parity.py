@@ -104,6 +104,32 @@ def test_level_sigma_paths(team, probe):
             assert_same(gpu_run(g, eps, 0.1, seed, n_check, team=team, probe_min=probe), want)
 
 
+def _broom(handle, leaves):
+    """A path of `handle` vertices whose last vertex is the center of a star."""
+    u = list(range(handle - 1)) + [handle - 1] * leaves
+    v = list(range(1, handle)) + list(range(handle, handle + leaves))
+    return G.from_edges(handle + leaves, np.array(u), np.array(v), name=f"broom{handle}_{leaves}")
+
+
+@pytest.mark.parametrize("team", [64, 256])
+def test_relabelled_graphs(team):
+    """High-diameter graphs run in an internal vertex order (reverse
+    Cuthill-McKee) with every tie still broken by original id: the results
+    equal the oracle's.  Meeting sets larger than a 64-lane team (grid), and
+    backtracking through a hub by the level-list search (broom)."""
+    cases = [(G.cycle_graph(300), 0.05, 128), (G.path_graph(200), 0.05, 100),
+             (G.grid_graph(100, 100), 0.05, 256), (_broom(100, 500), 0.05, 128),
+             (G.disjoint_union(G.path_graph(150), G.grid_graph(9, 9)), 0.05, 64)]
+    for g, eps, n_check in cases:
+        print(f"case relabelled {g.name} team={team}", flush=True)
+        with Graph.from_csr(g) as dev:
+            assert dev.get_param("relabeled") == 1
+        for seed in (1, 6):
+            assert_same(gpu_run(g, eps, 0.1, seed, n_check, team=team), oracle.run(g, eps, 0.1, seed, n_check))
+    with Graph.from_csr(G.erdos_renyi(500, 6.0, seed=3)) as dev:
+        assert dev.get_param("relabeled") == 0  # low diameter: original order
+
+
 def test_layered_graph_with_huge_sigma():
     # 17^(d-1) shortest paths: sigma beyond 2^104 forces level rescaling
     width, layers = 17, 80
