@@ -83,6 +83,10 @@ typedef struct {
  *   col_idx  host int32[num_arcs]; each row strictly ascending, entries in
  *            [0, n), no self-loops, and (u, v) present iff (v, u) present
  *   out      receives the handle (NULL on failure)
+ * A graph whose vertex-diameter bound is 64 or more is stored on the device in
+ * a reverse Cuthill-McKee vertex order (computed on the host), which keeps
+ * the search balls of high-diameter graphs compact in memory; every result
+ * and every output is still in, and tie-broken by, the given vertex ids.
  * The caller keeps ownership of its arrays.  Errors: EINVAL (malformed CSR),
  * ERANGE (n or a degree >= 2^23), ENOMEM, EDEVICE.
  */
@@ -138,7 +142,11 @@ int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr,
  */
 int kadabra_set_param(kadabra_graph *g, const char *key, int64_t value);
 
-/* Reads a parameter set by kadabra_set_param (auto values read as 0). */
+/* Reads a parameter set by kadabra_set_param (auto values read as 0), or one
+ * of the graph's read-only values: "vd_bound" (the vertex-diameter bound),
+ * "components", "max_degree", "relabeled" (1: stored in the internal vertex
+ * order described at kadabra_create_graph, 0: in the given order), and the
+ * mapping of the last run, "last_team" and "last_slots". */
 int kadabra_get_param(const kadabra_graph *g, const char *key, int64_t *value);
 
 /*
