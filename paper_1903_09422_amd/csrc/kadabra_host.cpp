@@ -643,15 +643,25 @@ int Runner::start_query(Query &q, int64_t *fc)
             HIP_OR_FAIL(alloc_n((char **)&q.plan_buf, q.plan_bytes(), fc));
             q.plan_len = q.plan_bytes();
         }
-        HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)q.c1, n, 0u, stream));
-        HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)q.hist(), (size_t)(q.m1 + 1), 0u, stream));
     }
     if (free_cslots.empty()) return fail(KADABRA_ESTATE, "no free control block");
     q.cslot = free_cslots.back();
     free_cslots.pop_back();
-    HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)q.counts, n, 0u, stream));
-    HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)q.frames, q.frames_count(), 0u, stream));
-    HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)(d_ctl + q.cslot), sizeof(kd::Control) / 4, 0u, stream));
+    // counters, frames, control block (and the balancing buffers): one launch
+    kd::ZeroRegions z{};
+    auto zero = [&](void *p, size_t words) {
+        z.ptr[z.n] = (uint32_t *)p;
+        z.count[z.n] = words;
+        ++z.n;
+    };
+    zero(q.counts, n);
+    zero(q.frames, q.frames_count());
+    zero(d_ctl + q.cslot, sizeof(kd::Control) / 4);
+    if (q.m1 > 0) {
+        zero(q.c1, n);
+        zero(q.hist(), (size_t)(q.m1 + 1));
+    }
+    HIP_OR_FAIL(kd::launch_zero_regions(z, stream));
     q.k = q.merged = q.merged_prev = q.lo = 0;
     q.spec = false;
     q.first_launched = false;
@@ -834,14 +844,16 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
         // test hook: a smaller level capacity trips the sampler's level-bound
         // check (the level offsets of a slot then pack into a smaller stride)
         if (p.level_cap > 0 && p.level_cap < st.lcap) sa.st.lcap = p.level_cap;
-        claim_next += (uint64_t)total + (uint64_t)slots;  // every block makes one failing claim
+        // no more workgroups than samples (a small or gated launch starts fewer)
+        const int grid = (int)std::min<int64_t>(slots, std::max<int64_t>(total, 1));
+        claim_next += (uint64_t)total + (uint64_t)grid;  // every workgroup makes one failing claim
         L.e0 = take_event();
         L.e1 = take_event();
         if (!L.e0 || !L.e1) return fail(KADABRA_EDEVICE, "event creation failed");
         HIP_OR_FAIL(hipEventRecord(L.e0, stream));
         bool mapped = false;
         for (Query *q : qs) mapped = mapped || q->gd->d_perm != nullptr;
-        HIP_OR_FAIL(kd::launch_sample(team, (int)slots, sa, mapped, stream));
+        HIP_OR_FAIL(kd::launch_sample(team, grid, sa, mapped, stream));
         HIP_OR_FAIL(hipEventRecord(L.e1, stream));
         pend.push_back(std::move(L));
         // the balanced constants, from the finished first phase, before any check

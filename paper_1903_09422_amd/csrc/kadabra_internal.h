@@ -166,6 +166,16 @@ hipError_t launch_bfs_level(const int32_t *row_ptr, const int32_t *col, const in
                             const int32_t *count, int32_t frontier_size, int32_t level, int32_t *dist,
                             int32_t *next, int32_t *next_count, hipStream_t s);
 hipError_t launch_gather_i32(int32_t *dst, const int32_t *src, const int32_t *idx, int32_t n, hipStream_t s);
+
+// Several buffers zeroed by one launch (a query's counters, frames, control
+// block and balancing buffers).
+constexpr int kMaxZeroRegions = 5;
+struct ZeroRegions {
+    uint32_t *ptr[kMaxZeroRegions];
+    size_t count[kMaxZeroRegions];  // 32-bit words
+    int n;
+};
+hipError_t launch_zero_regions(const ZeroRegions &z, hipStream_t s);
 hipError_t launch_bfs_small(const int32_t *row_ptr, const int32_t *col, int32_t *dist, int32_t *q0, int32_t *q1,
                             int32_t *state, int32_t small_max, hipStream_t s);
 

@@ -296,4 +296,26 @@ hipError_t launch_gather_i32(int32_t *dst, const int32_t *src, const int32_t *id
     return hipGetLastError();
 }
 
+// Zeroes up to kMaxZeroRegions device regions in one launch: block (x, y)
+// strides over region y.
+__global__ void zero_regions_kernel(ZeroRegions z)
+{
+    const int r = (int)blockIdx.y;
+    uint32_t *const p = z.ptr[r];
+    const size_t count = z.count[r];
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x)
+        p[k] = 0u;
+}
+
+hipError_t launch_zero_regions(const ZeroRegions &z, hipStream_t s)
+{
+    if (z.n <= 0) return hipSuccess;
+    size_t most = 1;
+    for (int r = 0; r < z.n; ++r) most = z.count[r] > most ? z.count[r] : most;
+    size_t g = (most + 255) / 256;
+    if (g > 2048) g = 2048;
+    hipLaunchKernelGGL(zero_regions_kernel, dim3((unsigned)g, (unsigned)z.n), dim3(256), 0, s, z);
+    return hipGetLastError();
+}
+
 }  // namespace kd
