@@ -39,16 +39,21 @@ def algorithmic_bytes(stats: dict) -> int:
     return sum(BYTES_PER[k] * int(stats[k]) for k in BYTES_PER)
 
 
-def cpu_baseline(g, eps, delta, seed, n_check, repeats):
+def cpu_baseline(g, eps, delta, seed, n_check, min_seconds, max_repeats):
+    """Complete oracle runs of the same query, repeated until min_seconds of
+    CPU work have been timed (at least one run, at most max_repeats)."""
     import oracle
 
     oracle.lib()
     t0 = time.perf_counter()
-    samples = 0
-    for _ in range(repeats):
+    samples = repeats = 0
+    while True:
         r = oracle.run(g, eps, delta, seed, n_check)
         samples += r.tau
-    dt = time.perf_counter() - t0
+        repeats += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds or repeats >= max_repeats:
+            break
     return {"value": samples / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
             "sample": f"{repeats} complete oracle run(s) of the same workload and seed "
                       f"(tau={r.tau} each), single-threaded, {dt:.1f} s"}
@@ -73,7 +78,9 @@ def main() -> int:
     ap.add_argument("--probe-min", type=int, default=-1)
     ap.add_argument("--balanced-steps", type=int, default=10,
                     help="queries of the balanced leg (per-vertex delta_L, delta_U); 0: skip it")
-    ap.add_argument("--cpu-repeats", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="CPU oracle leg: repeat complete runs until this much time is timed")
+    ap.add_argument("--cpu-repeats", type=int, default=50, help="CPU oracle leg: at most this many runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--traffic-json", default=None,
                     help="HBM bytes per sampler launch from rocprofv3 counters (default: "
@@ -198,7 +205,8 @@ def main() -> int:
     if args.balanced_steps > 0:
         out["balanced"] = balanced_leg(dev, step, stream, args, dt * 1e3 / args.steps)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(g, eps, delta, args.seed, n_check, args.cpu_repeats)
+        out["cpu_baseline"] = cpu_baseline(g, eps, delta, args.seed, n_check, args.cpu_seconds,
+                                           args.cpu_repeats)
     dev.close()
     print(json.dumps(out))
     return 0
