@@ -565,15 +565,25 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
     for (;;) {
         __syncthreads();
         if (lane == 0) {
-            const int64_t j = (int64_t)(atomicAdd(a.claim, 1ull) - a.claim_base);
+            int64_t j;
             int32_t qi = 0;
-            if (j < a.total) {  // the query whose range holds claim j
-                int32_t lo = 0, hi = a.nq;
+            for (;;) {
+                j = (int64_t)(atomicAdd(a.claim, 1ull) - a.claim_base);
+                if (j >= a.total) break;
+                int32_t lo = 0, hi = a.nq;  // the query whose range holds claim j
                 while (hi - lo > 1) {
                     const int32_t mid = (lo + hi) >> 1;
                     if (a.q[mid].claim_begin <= j) lo = mid; else hi = mid;
                 }
                 qi = lo;
+                // Launched before the host has read the previous boundary's
+                // check: stream order has already run that check, so its flag
+                // decides.  A stopped run's range needs no claims: the counter
+                // moves past it at once (never past the launch's total, so
+                // every workgroup still ends on exactly one failing claim).
+                const QueryDesc &d = a.q[qi];
+                if (d.gate < 0 || d.ctl->viol[d.gate] != 0) break;
+                atomicMax(a.claim, (unsigned long long)(a.claim_base + (uint64_t)(d.claim_begin + (d.hi - d.lo))));
             }
             sm.claim = j;
             sm.query = qi;
@@ -584,10 +594,6 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
         // the query's fields, once, into scalar registers
         const QueryDesc *const qd = a.q + uniform_i32(sm.query);
         Control *const qctl = qd->ctl;
-        const int32_t qgate = qd->gate;
-        // launched before the host has read the previous boundary's check:
-        // stream order has already run that check, so its flag decides
-        if (qgate >= 0 && qctl->viol[qgate] == 0) continue;
         const int64_t i = qd->lo + (jc - qd->claim_begin);
         const int32_t qpar = (int32_t)((i / qd->epoch_len + 1) % qd->nsets);  // the epoch's set
         const int32_t qstat = qd->stat_set >= 0 ? qd->stat_set : qpar;       // its work counters
