@@ -837,6 +837,8 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
         kd::SampleArgs sa{};
         sa.q = d_qt[r];
         sa.nq = (int32_t)nd;
+        sa.gated = 1;
+        for (size_t k = 0; k < nd; ++k) sa.gated &= h[k].gate >= 0 ? 1 : 0;
         sa.total = total;
         sa.claim = d_claim;
         sa.claim_base = claim_next;

@@ -94,7 +94,7 @@ struct QueryDesc {
 struct SampleArgs {
     const QueryDesc *q;   // queries of this launch, by increasing claim_begin
     int32_t nq;
-    int32_t pad;
+    int32_t gated;        // 1: every query of the launch has a gate (a speculative launch)
     int64_t total;        // samples of this launch
     unsigned long long *claim;  // monotone claim counter
     uint64_t claim_base;  // its value when this launch starts

@@ -544,6 +544,24 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 d.ctl->viol[e % d.nsets] = 0;
         }
 
+    // A speculative launch whose runs have all stopped at the previous
+    // boundary draws nothing.  Those flags were written earlier in stream order
+    // and do not change during the launch, so every workgroup decides alike and
+    // leaves; workgroup 0 moves the claim counter by what the claims would have
+    // taken (the samples, and one failing claim per workgroup).
+    if (a.gated) {
+        int open = 0;
+        for (int32_t k = lane; k < a.nq; k += TEAM) {
+            const QueryDesc &d = a.q[k];
+            open |= d.ctl->viol[d.gate] != 0 ? 1 : 0;
+        }
+        if (!__syncthreads_or(open)) {
+            if (blockIdx.x == 0 && lane == 0)
+                atomicAdd(a.claim, (unsigned long long)a.total + (unsigned long long)gridDim.x);
+            return;
+        }
+    }
+
 #ifdef KADABRA_PHASE_TIMERS
     uint64_t ph_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     Control *ph_ctl = nullptr;
