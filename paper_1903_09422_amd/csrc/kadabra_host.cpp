@@ -649,6 +649,8 @@ int Runner::start_query(Query &q, int64_t *fc)
     free_cslots.pop_back();
     // counters, frames, control block (and the balancing buffers): one launch
     kd::ZeroRegions z{};
+    static_assert(sizeof(kd::Control) % 4 == 0, "the control block is cleared as 32-bit words");
+    static_assert(kd::kMaxZeroRegions >= 5, "counters, frames, control block, c1, histogram");
     auto zero = [&](void *p, size_t words) {
         z.ptr[z.n] = (uint32_t *)p;
         z.count[z.n] = words;

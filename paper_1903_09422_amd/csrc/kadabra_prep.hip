@@ -310,6 +310,7 @@ __global__ void zero_regions_kernel(ZeroRegions z)
 hipError_t launch_zero_regions(const ZeroRegions &z, hipStream_t s)
 {
     if (z.n <= 0) return hipSuccess;
+    if (z.n > kMaxZeroRegions) return hipErrorInvalidValue;
     size_t most = 1;
     for (int r = 0; r < z.n; ++r) most = z.count[r] > most ? z.count[r] : most;
     size_t g = (most + 255) / 256;
