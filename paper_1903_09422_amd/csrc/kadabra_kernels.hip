@@ -744,6 +744,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
             // (a retry reads the cache again) nor when the level may rescale.
             const bool lds_try = !probe && fhix - flox <= TEAM && dsx <= (int64_t)ARCS * TEAM &&
                                  bitw128(X ? fmass1 : fmass0) <= SIGMA_BITS;
+            const bool low_mass = bitw128(X ? fmass1 : fmass0) <= 63;
             int32_t *const hkeys = reinterpret_cast<int32_t *>(&sm.fsg[X][0]);  // 4 TEAM >= STAGE ints
             constexpr int32_t HMASK = STAGE - 1;
             constexpr int32_t HMAX = STAGE / 2;  // at most half of the slots are filled
@@ -853,9 +854,17 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     }
                 };
                 // sigma(w) += sigma(owner) for every arc into the new level, in
-                // global memory: all low-word adds first, then the carries
+                // global memory: all low-word adds first, then the carries.  When
+                // the frontier's mass is below 2^63 no count of the new level can
+                // leave the low word, so the adds need no result and no wait.
                 auto global_adds = [&](const int32_t (&wv)[ARCS], const int32_t (&ow)[ARCS],
                                        const bool (&add)[ARCS]) {
+                    if (low_mass) {
+#pragma unroll
+                        for (int k = 0; k < ARCS; ++k)
+                            if (add[k]) (void)wg_add_u64(&sigx[wv[k]].lo, sm.cm[ow[k]].lo);
+                        return;
+                    }
                     uint64_t olo[ARCS];
 #pragma unroll
                     for (int k = 0; k < ARCS; ++k) olo[k] = 0u;
