@@ -81,16 +81,6 @@ __device__ __forceinline__ uint32_t wg_or_u32(uint32_t *p, uint32_t v)
 __device__ __forceinline__ uint32_t level_code(int32_t level) { return (uint32_t)(level % 3) + 1u; }
 __device__ __forceinline__ int code_shift(int32_t w, int side) { return 4 * (w & 7) + 2 * side; }
 
-// 128-bit add into global memory: low word atomically, carry into the high
-// word.  The final value is the exact sum whatever the order of the adds.
-__device__ __forceinline__ void atomic_add_sigma(Sigma *p, u128 v)
-{
-    const uint64_t lo = (uint64_t)v;
-    const uint64_t old = wg_add_u64(&p->lo, lo);
-    const uint64_t hi = (uint64_t)(v >> 64) + ((old + lo) < old ? 1u : 0u);
-    if (hi) wg_add_u64(&p->hi, hi);
-}
-
 // floor(u * m / 2^64) for 64-bit u and 128-bit m < 2^127
 __device__ __forceinline__ u128 mulhi_64x128(uint64_t u, u128 m)
 {
@@ -891,8 +881,14 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     __syncthreads();  // the claims are done and the set is filled
                     if (uniform_i32(*cnt_new) <= HMAX) {
 #pragma unroll
-                        for (int k = 0; k < ARCS; ++k)
-                            if (add[k]) lds_add128(&sm.sw[hash_find(hkeys, HMASK, wv[k])], sm.cm[ow[k]]);
+                        for (int k = 0; k < ARCS; ++k) {
+                            if (!add[k]) continue;
+                            Sigma *const q = &sm.sw[hash_find(hkeys, HMASK, wv[k])];
+                            if (low_mass)  // no carry possible: an add without a result
+                                (void)atomicAdd((unsigned long long *)&q->lo, (unsigned long long)sm.cm[ow[k]].lo);
+                            else
+                                lds_add128(q, sm.cm[ow[k]]);
+                        }
                     } else {
                         global_adds(wv, ow, add);
                     }
