@@ -652,8 +652,16 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
 
         // -- balanced bidirectional BFS with path counts ----------------------
         if (lane == 0) {
-            code[s >> 3] |= level_code(0) << code_shift(s, 0);
-            code[t >> 3] |= level_code(0) << code_shift(t, 1);
+            // every code word is zero between samples (each sample clears the
+            // words it touched), so s and t are entered by stores, with no read
+            const uint32_t cs0 = level_code(0) << code_shift(s, 0);
+            const uint32_t ct1 = level_code(0) << code_shift(t, 1);
+            if ((s >> 3) == (t >> 3)) {
+                code[s >> 3] = cs0 | ct1;
+            } else {
+                code[s >> 3] = cs0;
+                code[t >> 3] = ct1;
+            }
             sig0[s] = Sigma{1u, 0u};
             sig1[t] = Sigma{1u, 0u};
             ball0[0] = s;
