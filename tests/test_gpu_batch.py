@@ -111,3 +111,35 @@ def test_autotune_is_result_neutral():
         got = dev.result()
     assert got.tau == ref["tau"]
     assert hashlib.sha256(got.counts.astype("<i4").tobytes()).hexdigest() == ref["counts_sha256"]
+
+
+def test_stopped_runs_in_speculative_launches():
+    """The launch queued after a boundary is gated on that boundary's check.
+    When every run of it has stopped, its workgroups leave at once; beside a
+    run that goes on, a stopped run's claims are skipped.  Either way the claim
+    counter ends where the next launch expects it, so repeated runs on the same
+    handle or batch still equal the oracle."""
+    a = (G.erdos_renyi(600, 6.0, seed=11), 0.05, 128)  # stops by the rule at 1024 of omega = 1400
+    b = (G.grid_graph(20, 20), 0.05, 64)                # stops by the rule at 1536 of omega = 2000
+    want_a = {s: oracle.run(a[0], a[1], 0.1, s, a[2]) for s in (1, 2)}
+    want_b = oracle.run(b[0], b[1], 0.1, 1, b[2])
+    assert want_a[1].tau < want_a[1].stats["omega"] and want_b.tau < want_b.stats["omega"]
+    assert want_a[1].tau < want_b.tau  # a stops while b goes on
+    ha, hb = Graph.from_csr(a[0]), Graph.from_csr(b[0])
+    for epl in (1, 2):
+        print(f"case stopped runs, epochs_per_launch={epl}", flush=True)
+        ha.set_param("check_interval", a[2])
+        ha.set_param("epochs_per_launch", epl)
+        for s in (1, 2, 1):
+            ha.run(a[1], 0.1, s)
+            _same(ha.result(), want_a[s])
+        with Batch() as bt:
+            bt.set_param("epochs_per_launch", epl)
+            bt.add(ha, a[1], 0.1, 1, a[2])
+            bt.add(hb, b[1], 0.1, 1, b[2])
+            for _ in range(2):
+                bt.run()
+                _same(bt.result(0), want_a[1])
+                _same(bt.result(1), want_b)
+    ha.close()
+    hb.close()
