@@ -449,6 +449,27 @@ __device__ __forceinline__ void pick_by_id_prefix(const int32_t *sv, const Sigma
     }
 }
 
+// The same for weights whose total is below 2^64 (the meeting draw's 40-bit
+// weights): 64-bit prefixes, four entries per step.
+template <int TEAM>
+__device__ __forceinline__ void pick_by_id_prefix64(const int32_t *sv, const Sigma *sw, int32_t cnt,
+                                                    uint64_t r, int32_t *pick)
+{
+    for (int32_t k = threadIdx.x; k < cnt; k += TEAM) {
+        const int32_t c = sv[k];
+        uint64_t pre = 0;
+        int32_t j = 0;
+        for (; j + 4 <= cnt; j += 4) {
+            const int32_t v0 = sv[j], v1 = sv[j + 1], v2 = sv[j + 2], v3 = sv[j + 3];
+            const uint64_t w0 = sw[j].lo, w1 = sw[j + 1].lo, w2 = sw[j + 2].lo, w3 = sw[j + 3].lo;
+            pre += (v0 <= c ? w0 : 0u) + (v1 <= c ? w1 : 0u) + (v2 <= c ? w2 : 0u) + (v3 <= c ? w3 : 0u);
+        }
+        for (; j < cnt; ++j) pre += (sv[j] <= c) ? sw[j].lo : 0u;
+        const uint64_t wk = sw[k].lo;
+        if (pre > r && pre - wk <= r) *pick = c;
+    }
+}
+
 // An open-addressing set of vertex ids in LDS: mask + 1 slots (a power of
 // two), -1 = empty, linear probing.  Filled to at most half, so every probe
 // sequence ends.
@@ -1047,7 +1068,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 // ascending-id inclusive prefix first exceeds r
                 if (lane == 0) sm.pick = -1;
                 __syncthreads();  // also: the staged weights are visible
-                pick_by_id_prefix<TEAM>(sm.sv, sm.sw, nM, (u128)r, &sm.pick);
+                pick_by_id_prefix64<TEAM>(sm.sv, sm.sw, nM, r, &sm.pick);
                 __syncthreads();
                 v = uniform_i32(sm.pick);
                 if (MAPPED && qd->perm) v = qd->perm[v];
