@@ -920,10 +920,15 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
                 m.block_begin = blocks;
                 blocks += kd::merge_blocks_for(q.gd->n);
             }
-            HIP_OR_FAIL(hipMemcpyAsync(d_mt[r], h, (size_t)nq * sizeof(kd::MergeDesc), hipMemcpyHostToDevice,
-                                       stream));
             kd::MergeArgs ma{};
-            ma.m = d_mt[r];
+            if (nq == 1) {  // in the launch's arguments
+                ma.m = nullptr;
+                ma.one = h[0];
+            } else {
+                HIP_OR_FAIL(hipMemcpyAsync(d_mt[r], h, (size_t)nq * sizeof(kd::MergeDesc),
+                                           hipMemcpyHostToDevice, stream));
+                ma.m = d_mt[r];
+            }
             ma.nq = nq;
             ma.nblocks = blocks;
             HIP_OR_FAIL(kd::launch_merge_check(ma, stream));

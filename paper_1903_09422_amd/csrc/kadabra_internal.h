@@ -123,9 +123,10 @@ struct MergeDesc {
 };
 
 struct MergeArgs {
-    const MergeDesc *m;
-    int32_t nq;
+    const MergeDesc *m;   // the queries' descriptors in device memory; null: the one query
+    int32_t nq;           // is `one`, passed in the arguments (no copy before the launch)
     int32_t nblocks;
+    MergeDesc one;
 };
 
 // Balancing of delta_L(v), delta_U(v) from the first-phase counters c1:

@@ -1333,15 +1333,24 @@ int32_t merge_blocks_for(int32_t n)
 
 __global__ __launch_bounds__(MERGE_BLOCK) void merge_check_kernel(MergeArgs a)
 {
-    // the query whose block range holds this block
-    int32_t lo = 0, hi = a.nq;
-    while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (a.m[mid].block_begin <= (int32_t)blockIdx.x) lo = mid; else hi = mid;
+    // the query whose block range holds this block (one query travels in the
+    // arguments)
+    MergeDesc M;
+    int32_t qb, nb;
+    if (!a.m) {
+        M = a.one;
+        qb = (int32_t)blockIdx.x;
+        nb = a.nblocks;
+    } else {
+        int32_t lo = 0, hi = a.nq;
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (a.m[mid].block_begin <= (int32_t)blockIdx.x) lo = mid; else hi = mid;
+        }
+        M = a.m[lo];
+        qb = (int32_t)blockIdx.x - M.block_begin;
+        nb = ((lo + 1 < a.nq) ? a.m[lo + 1].block_begin : a.nblocks) - M.block_begin;
     }
-    const MergeDesc &M = a.m[lo];
-    const int32_t qb = (int32_t)blockIdx.x - M.block_begin;
-    const int32_t nb = ((lo + 1 < a.nq) ? a.m[lo + 1].block_begin : a.nblocks) - M.block_begin;
     // the run stopped at the previous boundary: leave its counters as they are
     if (M.gate >= 0 && M.ctl->viol[M.gate] == 0) return;
     const size_t n = (size_t)M.n;
