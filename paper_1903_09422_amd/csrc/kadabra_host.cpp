@@ -480,7 +480,8 @@ struct Runner {
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) num_cu = prop.multiProcessorCount;
         HIP_OR_FAIL(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
         stream = own_stream;
-        HIP_OR_FAIL(hipEventCreate(&ev_round));
+        // only waited for, never timed
+        HIP_OR_FAIL(hipEventCreateWithFlags(&ev_round, hipEventDisableTiming));
         HIP_OR_FAIL(alloc_n(&d_claim, 1));
         // zeroed on the runner's stream and waited for: every later launch,
         // on whichever stream, sees the counter at claim_next = 0
