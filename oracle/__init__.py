@@ -107,6 +107,10 @@ def lib():
         L.oracle_sample.argtypes = [C.c_int32, i32p, i32p, i32p, C.c_uint64, C.c_uint64, i32p,
                                     C.POINTER(SampleInfo)]
         L.oracle_sample.restype = C.c_int32
+        L.oracle_sample_pair.argtypes = [C.c_int32, i32p, i32p, i32p, C.c_uint64, C.c_int32,
+                                         C.c_int32, C.c_uint64, C.c_int64, C.c_int32, i32p, i32p,
+                                         C.POINTER(SampleInfo)]
+        L.oracle_sample_pair.restype = C.c_int32
         L.oracle_accumulate.argtypes = [C.c_int32, i32p, i32p, i32p, C.c_uint64, C.c_uint64,
                                         C.c_uint64, i64p]
         L.oracle_accumulate.restype = C.c_int64
@@ -266,6 +270,24 @@ def sample(g, comp, seed: int, i: int):
     if k == -2:
         raise MemoryError
     return (None if k < 0 else out[:k].copy()), info
+
+
+def sample_pair(g, comp, seed: int, s: int, t: int, i0: int, count: int):
+    """count samples (indices i0 ...) at the fixed pair (s, t): (interior
+    vertices per sample as a (count, d - 1) array, meeting vertex per sample,
+    SampleInfo of the first sample)."""
+    n, rp, col = _csr(g)
+    stride = max(n, 1)
+    paths = np.zeros((count, stride), dtype=np.int32)
+    meet = np.zeros(count, dtype=np.int32)
+    info = SampleInfo()
+    k = lib().oracle_sample_pair(n, rp, col, np.ascontiguousarray(comp, dtype=np.int32), seed,
+                                 s, t, i0, count, stride, paths, meet, C.byref(info))
+    if k == -2:
+        raise MemoryError
+    if k < 0:
+        raise ValueError(f"pair ({s}, {t}) not connected or bad stride ({k})")
+    return paths[:, :k].copy(), meet, info
 
 
 def accumulate(g, comp, seed: int, i0: int, i1: int) -> tuple:

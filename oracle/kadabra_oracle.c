@@ -27,8 +27,9 @@
  *     paper it cites, so the rule used here is a reading, derived below).
  * Readings of points on which the paper is silent (the balanced bidirectional
  * BFS rule, the omega formula, uniform delta_L/delta_U, the balancing rule,
- * the block-float sigma representation, the random-draw assignment) are
- * listed with the function that takes them.
+ * exact 128-bit sigma that a level divides by a power of two only beyond
+ * 2^104, the 40-bit meeting weights, the random-draw assignment) are listed
+ * with the function that takes them.
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared (no fast-math: the
  * stop test must evaluate the exact IEEE expression tree given below).
@@ -506,11 +507,13 @@ static void sampler_free(struct sampler *S)
  * components (the sample then adds nothing).  Optional outputs describe the
  * search for the tests. */
 static int32_t sample_path(struct sampler *S, uint64_t seed, uint64_t i, int32_t *interior,
-                           oracle_sample_info *info, oracle_stats *st)
+                           oracle_sample_info *info, oracle_stats *st, int32_t s_given,
+                           int32_t t_given)
 {
     const int32_t *row_ptr = S->row_ptr, *col = S->col;
     int32_t s, t;
-    oracle_pair(seed, i, S->n, &s, &t);
+    if (s_given >= 0) { s = s_given; t = t_given; }  /* a fixed pair (path-law tests) */
+    else oracle_pair(seed, i, S->n, &s, &t);
     if (info) { memset(info, 0, sizeof(*info)); info->s = s; info->t = t; info->d = -1; }
     /* Appendix C.1: no search between different components */
     if (S->comp[s] != S->comp[t]) return -1;
@@ -717,7 +720,7 @@ static int first_phase(struct sampler *S, int32_t n, uint64_t seed, int64_t m1, 
 {
     for (int32_t v = 0; v < n; ++v) c1[v] = 0;
     for (int64_t m = 0; m < m1; ++m) {
-        int32_t ni = sample_path(S, seed, FIRST_PHASE_BASE + (uint64_t)m, interior, NULL, st);
+        int32_t ni = sample_path(S, seed, FIRST_PHASE_BASE + (uint64_t)m, interior, NULL, st, -1, -1);
         if (ni < 0) { st->disconnected += 1; continue; }
         for (int32_t q = 0; q < ni; ++q) c1[interior[q]] += 1;
     }
@@ -782,7 +785,7 @@ int oracle_run_balanced(int32_t n, const int32_t *row_ptr, const int32_t *col, d
         if (hi > omega) hi = omega;
         if (sample_cap >= 0 && hi > sample_cap) hi = sample_cap;
         for (int64_t i = tau; i < hi; ++i) {
-            int32_t ni = sample_path(&S, seed, (uint64_t)i, interior, NULL, st);
+            int32_t ni = sample_path(&S, seed, (uint64_t)i, interior, NULL, st, -1, -1);
             if (ni < 0) { st->disconnected += 1; continue; }
             for (int32_t q = 0; q < ni; ++q) counts[interior[q]] += 1;
         }
@@ -822,9 +825,41 @@ int32_t oracle_sample(int32_t n, const int32_t *row_ptr, const int32_t *col, con
 {
     struct sampler S;
     if (sampler_init(&S, n, row_ptr, col, comp) != 0) return -2;
-    int32_t r = sample_path(&S, seed, i, interior, info, NULL);
+    int32_t r = sample_path(&S, seed, i, interior, info, NULL, -1, -1);
     sampler_free(&S);
     return r;
+}
+
+/* Samples i0 .. i0 + count - 1 with the pair (s, t) given instead of drawn
+ * (s != t, one component): draw 0 is unused, draws j >= 1 of each sample pick
+ * the meeting vertex and the predecessors as in any sample.  For the
+ * path-law tests at one pair.  Writes sample k's interior vertices (their
+ * order as in oracle_sample) to paths[k stride ...] (stride >= d - 1), its
+ * meeting vertex to meet[k], and the first sample's description to *info.
+ * Returns the number of interior vertices per sample (the same for every
+ * sample of one pair), -1 if s and t lie in different components, -2 on a
+ * failed allocation, -3 if stride is too small. */
+int32_t oracle_sample_pair(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                           const int32_t *comp, uint64_t seed, int32_t s, int32_t t, uint64_t i0,
+                           int64_t count, int32_t stride, int32_t *paths, int32_t *meet,
+                           oracle_sample_info *info)
+{
+    struct sampler S;
+    oracle_sample_info one;
+    int32_t *interior = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!interior || sampler_init(&S, n, row_ptr, col, comp) != 0) { free(interior); return -2; }
+    int32_t ni = 0;
+    for (int64_t k = 0; k < count; ++k) {
+        ni = sample_path(&S, seed, i0 + (uint64_t)k, interior, &one, NULL, s, t);
+        if (k == 0 && info) *info = one;
+        if (ni < 0) break;
+        if (ni > stride) { ni = -3; break; }
+        memcpy(paths + (size_t)k * (size_t)stride, interior, sizeof(int32_t) * (size_t)ni);
+        meet[k] = one.meet_vertex;
+    }
+    sampler_free(&S);
+    free(interior);
+    return ni;
 }
 
 /* Sum of x_i(v) over samples [i0, i1) without any stopping rule (for the
@@ -838,7 +873,7 @@ int64_t oracle_accumulate(int32_t n, const int32_t *row_ptr, const int32_t *col,
     if (!interior || sampler_init(&S, n, row_ptr, col, comp) != 0) return -2;
     int64_t connected = 0;
     for (uint64_t i = i0; i < i1; ++i) {
-        int32_t ni = sample_path(&S, seed, i, interior, NULL, NULL);
+        int32_t ni = sample_path(&S, seed, i, interior, NULL, NULL, -1, -1);
         if (ni < 0) continue;
         ++connected;
         for (int32_t q = 0; q < ni; ++q) acc[interior[q]] += 1;

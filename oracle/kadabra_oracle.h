@@ -74,6 +74,10 @@ int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, double eps
                oracle_stats *st, int8_t *decisions, int64_t max_decisions);
 int32_t oracle_sample(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *comp,
                       uint64_t seed, uint64_t i, int32_t *interior, oracle_sample_info *info);
+int32_t oracle_sample_pair(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                           const int32_t *comp, uint64_t seed, int32_t s, int32_t t, uint64_t i0,
+                           int64_t count, int32_t stride, int32_t *paths, int32_t *meet,
+                           oracle_sample_info *info);
 int64_t oracle_accumulate(int32_t n, const int32_t *row_ptr, const int32_t *col,
                           const int32_t *comp, uint64_t seed, uint64_t i0, uint64_t i1,
                           int64_t *acc);

@@ -127,12 +127,18 @@ int validate_csr(int32_t n, int64_t num_arcs, const int32_t *row_ptr, const int3
     if ((int64_t)row_ptr[n] != num_arcs)
         return fail(KADABRA_EINVAL, "row_ptr[n] (%d) != num_arcs (%lld)", row_ptr[n],
                     (long long)num_arcs);
+    // every row bound first: non-decreasing from 0, so each lies in
+    // [0, num_arcs], and only then any read of col
     int32_t max_deg = 0;
     for (int32_t v = 0; v < n; ++v) {
         if (row_ptr[v + 1] < row_ptr[v])
             return fail(KADABRA_EINVAL, "row_ptr decreases at %d", v);
-        const int32_t deg = row_ptr[v + 1] - row_ptr[v];
-        max_deg = std::max(max_deg, deg);
+        if ((int64_t)row_ptr[v + 1] > num_arcs)
+            return fail(KADABRA_EINVAL, "row_ptr[%d] (%d) exceeds num_arcs (%lld)", v + 1,
+                        row_ptr[v + 1], (long long)num_arcs);
+        max_deg = std::max(max_deg, row_ptr[v + 1] - row_ptr[v]);
+    }
+    for (int32_t v = 0; v < n; ++v) {
         for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
             const int32_t w = col[e];
             if (w < 0 || w >= n) return fail(KADABRA_EINVAL, "column %d out of range at row %d", w, v);

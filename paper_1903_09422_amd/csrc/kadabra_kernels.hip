@@ -523,6 +523,11 @@ template <int TEAM, bool MAPPED>
 __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void sample_kernel(SampleArgs a)
 {
     using T = Team<TEAM>;
+#ifdef KADABRA_PHASE_TIMERS
+    // The one-wavefront timer build gave a wrong result once (a backtracking
+    // step found no predecessor) and its cause is not known: it is not built.
+    static_assert(TEAM != 64, "phase timers are not available for 64-lane teams");
+#endif
     constexpr int ARCS = (TEAM == 64) ? 4 : 8;     // arcs in flight per lane in a level expansion
     constexpr int STAGE = Cap<TEAM>::STAGE;
     __shared__ SampleShared<TEAM> sm;
@@ -1419,9 +1424,12 @@ static unsigned grid_for(size_t count, unsigned block)
 template <bool MAPPED>
 static hipError_t launch_sample_as(int team, int slots, const SampleArgs &a, hipStream_t s)
 {
+#ifndef KADABRA_PHASE_TIMERS
     if (team == 64)
         hipLaunchKernelGGL((sample_kernel<64, MAPPED>), dim3(slots), dim3(64), 0, s, a);
-    else if (team == 128)
+    else
+#endif
+    if (team == 128)
         hipLaunchKernelGGL((sample_kernel<128, MAPPED>), dim3(slots), dim3(128), 0, s, a);
     else if (team == 256)
         hipLaunchKernelGGL((sample_kernel<256, MAPPED>), dim3(slots), dim3(256), 0, s, a);

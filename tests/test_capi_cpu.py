@@ -73,6 +73,43 @@ def test_create_rejects_malformed_csr():
     _ = asym
 
 
+def _guarded_i32(values):
+    """values in an int32 array that ends exactly at a PROT_NONE page, so a
+    read one element past its end faults instead of passing unnoticed."""
+    import mmap
+
+    page = mmap.PAGESIZE
+    buf = mmap.mmap(-1, 2 * page, prot=mmap.PROT_READ | mmap.PROT_WRITE)
+    base = C.addressof(C.c_char.from_buffer(buf))
+    libc = C.CDLL(None, use_errno=True)
+    libc.mprotect.argtypes = [C.c_void_p, C.c_size_t, C.c_int]
+    assert libc.mprotect(base + page, page, 0) == 0  # PROT_NONE
+    vals = np.asarray(values, dtype=np.int32)
+    arr = np.frombuffer(buf, dtype=np.int32, count=vals.size, offset=page - 4 * vals.size)
+    arr[:] = vals
+    return buf, arr
+
+
+def test_create_rejects_row_bound_past_arcs_before_reading_col():
+    """row_ptr = [0, 3, 3, 2] with num_arcs = 2: row 0 claims arcs 0..2, but
+    col has only two entries.  The bounds must be rejected before col is read
+    (col ends at a guard page here, so reading col[2] would fault)."""
+    buf, col = _guarded_i32([1, 2])
+    L = _lib.lib()
+    rp = np.array([0, 3, 3, 2], dtype=np.int32)
+    h = C.c_void_p(1234)
+    rc = L.kadabra_create_graph(3, 2, rp.ctypes.data, col.ctypes.data, C.byref(h))
+    err = L.kadabra_last_error().decode()
+    assert rc == _lib.EINVAL and h.value is None, (rc, err)
+    assert "exceeds num_arcs" in err, err
+    # a row bound past the arcs in the middle, the last one consistent
+    rp = np.array([0, 1, 5, 2], dtype=np.int32)
+    rc = L.kadabra_create_graph(3, 2, rp.ctypes.data, col.ctypes.data, C.byref(h))
+    assert rc == _lib.EINVAL and h.value is None
+    del col
+    buf.close()
+
+
 def test_create_rejects_oversize():
     n = 1 << 23
     rc, h, err = _create(n, np.zeros(n + 1, dtype=np.int32), np.zeros(0, dtype=np.int32))
