@@ -171,6 +171,37 @@ int kadabra_set_stream(kadabra_graph *g, void *hip_stream);
 int kadabra_run(kadabra_graph *g, double eps, double delta, uint64_t seed);
 
 /*
+ * kadabra_run for callers that cannot allocate memory: code being captured
+ * into a HIP graph, tight serving loops, and harnesses that forbid
+ * allocation.  It calls no hipMalloc, hipFree, hipHostMalloc or other
+ * allocating routine.  All run-time device state (sample slots, counter
+ * frames, control block, claim counter and launch descriptor) lives in one
+ * static device array of 256 MiB that the library holds on every GPU it runs
+ * on until the process ends; the array's device address is looked up once per
+ * device, on the first call there.
+ *   g          a graph from kadabra_create_graph, with its device current
+ *              (EINVAL otherwise); its "check_interval", "team", "slots" and
+ *              "probe_min" apply, "balance" must be 0 (EINVAL otherwise)
+ *   eps, delta, seed  as kadabra_run
+ *   counts_dev caller-allocated device int32[n]; receives the counters of the
+ *              tau samples, exactly those kadabra_run computes for the same
+ *              (graph, eps, delta, seed, check_interval)
+ *   stats      host kadabra_stats or NULL: tau, omega, vd_bound, epochs,
+ *              decision, the work counters, log_inv_delta and ms_total
+ * The run is blocking, one check interval per launch, on the handle's stream;
+ * samples in flight are as many as fit in the array (at most "slots" if set,
+ * else 1024).  The handle's last kadabra_run result is left as it is.
+ * The array is shared by every call on one GPU and keeps the last call's
+ * contents (each call clears what must start at zero): calls that overlap on
+ * one GPU race and must be serialised by the caller.
+ * Errors: EINVAL (null pointer, eps, delta, balance, device), ERANGE (omega
+ * >= 2^31, or the run state of one sample in flight, about 60 n bytes, does
+ * not fit in the array: use kadabra_run), EDEVICE, ECANCELED.
+ */
+int kadabra_run_static(kadabra_graph *g, double eps, double delta, uint64_t seed, int32_t *counts_dev,
+                       kadabra_stats *stats);
+
+/*
  * Reads the last completed run into caller-allocated host memory; any
  * pointer may be NULL.  scores: double[n], scores[v] = counts[v] / tau
  * (computed on the device); counts: int32[n]; stats: one kadabra_stats.

@@ -76,6 +76,16 @@ class Graph:
     def run(self, eps: float, delta: float, seed: int) -> None:
         check(lib().kadabra_run(self._h, float(eps), float(delta), int(seed)))
 
+    def run_static(self, eps: float, delta: float, seed: int, counts_dev) -> dict:
+        """kadabra_run_static: the run with all device state in the library's
+        static array (no allocation).  counts_dev: a device int32[n] tensor
+        (or a raw device address) that receives the counters.  Returns the
+        statistics."""
+        ptr = counts_dev if isinstance(counts_dev, int) else int(counts_dev.data_ptr())
+        st = Stats()
+        check(lib().kadabra_run_static(self._h, float(eps), float(delta), int(seed), ptr, C.byref(st)))
+        return st.as_dict()
+
     def cancel(self) -> None:
         check(lib().kadabra_cancel(self._h))
 

@@ -283,6 +283,7 @@ struct GraphData {
     int32_t max_deg = 0;
     int32_t vd = 1;
     int32_t ncomp = 0;
+    int device = 0;  // the HIP device holding the arrays
     int32_t *d_row_ptr = nullptr, *d_col = nullptr, *d_comp = nullptr;
     int32_t *d_colo = nullptr, *d_perm = nullptr, *d_iperm = nullptr;
     std::vector<int32_t> h_perm;  // host copy of d_perm (empty: identity)
@@ -1437,6 +1438,74 @@ kadabra_server::~kadabra_server()
         for (void *p : b.second) dev_free(p);
 }
 
+
+// ---------------------------------------------------------------------------
+// Run-time state in a static device array, for kadabra_run_static (callers
+// that may not allocate).  The array is part of the code object, so every GPU
+// the library runs on holds its own copy until the process ends.  Host code
+// never uses the name `scratch` as an address: the device address of each
+// GPU's copy comes from hipGetSymbolAddress, once per device.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_dev[kMaxStaticDevices] = {};
+
+// The device address of the current device's scratch array (looked up on the
+// first call on that device, with it current).
+int static_scratch(int dev, char **out)
+{
+    if (dev < 0 || dev >= kMaxStaticDevices) return fail(KADABRA_EDEVICE, "device %d beyond the static table", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(KADABRA_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_dev[dev] = (char *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return KADABRA_OK;
+}
+
+// Byte offsets of one static run's buffers in the scratch array: control
+// block, claim counter, launch descriptor, two frame sets, then the slot pool.
+struct StaticLayout {
+    size_t ctl, claim, desc, frames, code, sigma, ball, meet, meetw, loff, end;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+StaticLayout static_layout(int64_t n, int32_t lcap, int64_t slots)
+{
+    const size_t S = (size_t)slots, ns = (size_t)n;
+    StaticLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    L.ctl = take(sizeof(kd::Control));
+    L.claim = take(sizeof(unsigned long long));
+    L.desc = take(sizeof(kd::QueryDesc));
+    L.frames = take(2 * ns * sizeof(int32_t));
+    L.code = take(S * (size_t)code_stride_for(n) * sizeof(uint32_t));
+    L.sigma = take(S * 2 * ns * sizeof(kd::Sigma));
+    L.ball = take(S * 2 * ns * sizeof(int32_t));
+    L.meet = take(S * ns * sizeof(int32_t));
+    L.meetw = take(S * ns * sizeof(uint64_t));
+    L.loff = take(S * 2 * (size_t)lcap * sizeof(int32_t));
+    L.end = o;
+    return L;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *kadabra_last_error(void) { return g_last_error.c_str(); }
@@ -1580,6 +1649,7 @@ int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr, co
     gd.n = n;
     gd.arcs = num_arcs;
     gd.max_deg = max_deg;
+    HIP_OR_FAIL(hipGetDevice(&gd.device));
     OK_OR_RETURN(g->runner.init());
     struct {
         int32_t **dst;
@@ -1749,6 +1819,167 @@ int kadabra_eval_stop_fg(int32_t n, const int32_t *counts, int64_t tau, int64_t 
         return fail(KADABRA_EDEVICE, "eval_stop_fg: %s", hipGetErrorString(e));
     }
     cleanup();
+    return KADABRA_OK;
+}
+
+int kadabra_run_static(kadabra_graph *g, double eps, double delta, uint64_t seed, int32_t *counts_dev,
+                       kadabra_stats *stats)
+{
+    if (!g || !counts_dev) return fail(KADABRA_EINVAL, "null argument");
+    g_last_error.clear();
+    g->runner.cancel.store(0);
+    const auto t0 = std::chrono::steady_clock::now();
+    const GraphData &gd = g->gd;
+    const Params &p = g->params;
+    if (p.balance) return fail(KADABRA_EINVAL, "kadabra_run_static runs uniform delta_L, delta_U only (balance = 0)");
+    if (!(eps > 0.0 && eps < 1.0)) return fail(KADABRA_EINVAL, "eps must be in (0, 1)");
+    if (!(delta > 0.0 && delta < 1.0)) return fail(KADABRA_EINVAL, "delta must be in (0, 1)");
+    int dev = -1;
+    HIP_OR_FAIL(hipGetDevice(&dev));
+    if (dev != gd.device)
+        return fail(KADABRA_EINVAL, "the graph lives on device %d, the current device is %d", gd.device, dev);
+    const int64_t omega = omega_of(gd.vd, eps, delta);
+    if (omega > kMaxOmega || omega < 1)
+        return fail(KADABRA_ERANGE, "omega = %lld samples exceeds the int32 counters", (long long)omega);
+    const double L = std::log(4.0 * (double)gd.n / delta);
+    const int64_t N = p.check_interval;
+    const int32_t lcap = gd.vd + 2;
+    // as many samples in flight as the array holds (at most the "slots"
+    // parameter, else 1024)
+    int64_t slots = p.slots ? p.slots : 1024;
+    if (static_layout(gd.n, lcap, 1).end > kStaticScratchBytes)
+        return fail(KADABRA_ERANGE,
+                    "a graph of %d vertices needs %zu bytes of run state for one sample in flight; the static "
+                    "array holds %zu (use kadabra_run)",
+                    gd.n, static_layout(gd.n, lcap, 1).end, kStaticScratchBytes);
+    while (slots > 1 && static_layout(gd.n, lcap, slots).end > kStaticScratchBytes) {
+        const size_t per = static_layout(gd.n, lcap, 2).end - static_layout(gd.n, lcap, 1).end;
+        const size_t fixed = static_layout(gd.n, lcap, 1).end - per;
+        slots = std::min<int64_t>(slots - 1, (int64_t)((kStaticScratchBytes - fixed) / per));
+    }
+    slots = std::max<int64_t>(slots, 1);
+    const int team = p.team ? p.team : 256;
+    char *base = nullptr;
+    OK_OR_RETURN(static_scratch(dev, &base));
+    const StaticLayout lay = static_layout(gd.n, lcap, slots);
+    kd::Control *const ctl = (kd::Control *)(base + lay.ctl);
+    unsigned long long *const claim = (unsigned long long *)(base + lay.claim);
+    kd::QueryDesc *const desc = (kd::QueryDesc *)(base + lay.desc);
+    int32_t *const frames = (int32_t *)(base + lay.frames);
+    kd::SlotState st{};
+    st.code = (uint32_t *)(base + lay.code);
+    st.sigma = (kd::Sigma *)(base + lay.sigma);
+    st.ball = (int32_t *)(base + lay.ball);
+    st.meet = (int32_t *)(base + lay.meet);
+    st.meetw = (uint64_t *)(base + lay.meetw);
+    st.loff = (int32_t *)(base + lay.loff);
+    st.nstride = gd.n;
+    st.lcap = lcap;
+    st.code_stride = code_stride_for(gd.n);
+    const hipStream_t s = g->runner.stream;
+    // the array keeps the last call's contents: clear what must start at zero
+    // (counters, frames, control block and claim counter, code words, sigma)
+    kd::ZeroRegions z{};
+    auto zero = [&](void *ptr, size_t bytes) {
+        z.ptr[z.n] = (uint32_t *)ptr;
+        z.count[z.n] = bytes / 4;
+        ++z.n;
+    };
+    zero(counts_dev, (size_t)gd.n * sizeof(int32_t));
+    zero(ctl, lay.desc - lay.ctl);  // control block and claim counter
+    zero(frames, 2 * (size_t)gd.n * sizeof(int32_t));
+    zero(st.code, (size_t)slots * (size_t)st.code_stride * sizeof(uint32_t));
+    zero(st.sigma, (size_t)slots * 2 * (size_t)gd.n * sizeof(kd::Sigma));
+    HIP_OR_FAIL(kd::launch_zero_regions(z, s));
+    // one epoch per launch, checked before the next is queued
+    uint64_t claim_next = 0;
+    int64_t lo = 0, epochs = 0;
+    int decision = 0;
+    kd::Control h{};
+    while (decision == 0) {
+        const int64_t k = epochs + 1, hi = std::min<int64_t>(k * N, omega);
+        const int32_t set = (int32_t)(k % 2);
+        kd::QueryDesc d{};
+        d.row_ptr = gd.d_row_ptr;
+        d.col = gd.d_col;
+        d.comp = gd.d_comp;
+        d.perm = gd.d_perm;
+        d.iperm = gd.d_iperm;
+        d.colo = gd.d_colo;
+        d.frames = frames;
+        d.ctl = ctl;
+        d.seed = seed;
+        d.lo = lo;
+        d.hi = hi;
+        d.epoch_len = N;
+        d.claim_begin = 0;
+        d.probe_min = p.probe_min;
+        d.num_arcs = gd.arcs;
+        d.n = gd.n;
+        d.nframes = 1;
+        d.nsets = 2;
+        d.gate = -1;
+        d.stat_set = -1;
+        HIP_OR_FAIL(hipMemcpyAsync(desc, &d, sizeof d, hipMemcpyHostToDevice, s));
+        kd::SampleArgs sa{};
+        sa.q = desc;
+        sa.nq = 1;
+        sa.gated = 0;
+        sa.total = hi - lo;
+        sa.claim = claim;
+        sa.claim_base = claim_next;
+        sa.st = st;
+        const int grid = (int)std::min<int64_t>(slots, hi - lo);
+        claim_next += (uint64_t)(hi - lo) + (uint64_t)grid;
+        HIP_OR_FAIL(kd::launch_sample(team, grid, sa, gd.d_perm != nullptr, s));
+        kd::MergeArgs ma{};
+        ma.m = nullptr;
+        ma.nq = 1;
+        ma.nblocks = kd::merge_blocks_for(gd.n);
+        kd::MergeDesc &m = ma.one;
+        m.counts = counts_dev;
+        m.frames = frames + (size_t)set * (size_t)gd.n;
+        m.ctl = ctl;
+        m.perm = gd.d_perm;
+        m.tau = hi;
+        m.omega = omega;
+        m.L = L;
+        m.eps = eps;
+        m.n = gd.n;
+        m.nframes = 1;
+        m.set = set;
+        m.gate = -1;
+        m.do_check = hi < omega ? 1 : 0;
+        m.block_begin = 0;
+        HIP_OR_FAIL(kd::launch_merge_check(ma, s));
+        HIP_OR_FAIL(hipMemcpyAsync(&h, ctl, sizeof h, hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+        if (h.err)
+            return fail(KADABRA_EDEVICE, "device-side invariant failure %d in the sampler at sample %lld", h.err,
+                        (long long)h.err_sample);
+        epochs = k;
+        lo = hi;
+        if (hi == omega) decision = 2;
+        else if (h.viol[set] == 0) decision = 1;
+        else if (g->runner.cancel.load())
+            return fail(KADABRA_ECANCELED, "run canceled at %lld samples", (long long)hi);
+    }
+    if (stats) {
+        memset(stats, 0, sizeof *stats);
+        stats->tau = lo;
+        stats->omega = omega;
+        stats->vd_bound = gd.vd;
+        stats->epochs = epochs;
+        stats->decision = decision;
+        stats->v_exp = h.stats_total[kd::ST_VEXP];
+        stats->e_scan = h.stats_total[kd::ST_ESCAN];
+        stats->e_bt = h.stats_total[kd::ST_EBT];
+        stats->path_interior = h.stats_total[kd::ST_INTERIOR];
+        stats->disconnected = h.stats_total[kd::ST_DISCONN];
+        stats->log_inv_delta = L;
+        stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        stats->sample_launches = epochs;
+    }
     return KADABRA_OK;
 }
 
