@@ -122,6 +122,9 @@ int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr,
  *                     (by bisection) at which the summed probabilities fit in
  *                     0.9 delta/2, and 0.1 delta/2 is spread evenly on top;
  *                     if none fits below omega the uniform constants stay.
+ *                     t* and the constants are computed on the host from
+ *                     the histogram of c1 (summed over its nonzero rows in
+ *                     ascending count), with the C library's exp and log.
  *   "balance_samples" M1 >= 1 first-phase samples; 0 (default): ceil(omega/20).
  *   "probe_min"       k >= 0: expansions scanning at least k arcs first look
  *                     for the meeting set without materialising the new level;
@@ -129,11 +132,6 @@ int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr,
  *                     degree sums reaches four times the arc count.
  *   "test_fail_alloc" k >= 1: the k-th device allocation of the next run's
  *                     buffers fails with ENOMEM (failure-path testing); 0: off.
- *   "test_plan_cache_rows" k >= 1: the balancing plan keeps at most k nonzero
- *                     rows of the first-phase count histogram in LDS (more
- *                     rows than that are read from device memory at every
- *                     bisection step: the path taken when they do not fit);
- *                     0 (default): up to 4096.  Never changes results.
  *   "test_level_cap"  k >= 3: the sampler is given room for only k BFS levels
  *                     per side, so samples needing more fail its level-bound
  *                     check and the run ends with EDEVICE (failure-path

@@ -79,6 +79,7 @@ def lib():
         L.oracle_log_inv_delta.restype = C.c_double
         L.oracle_fg.argtypes = [C.c_int32, C.c_int64, C.c_int64, C.c_double,
                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.oracle_fg_batch.argtypes = [C.c_int64, i32p, C.c_int64, C.c_int64, C.c_double, f64p, f64p]
         L.oracle_check_stop.argtypes = [C.c_int32, i32p, C.c_int64, C.c_int64, C.c_double,
                                         C.c_double]
         L.oracle_check_stop.restype = C.c_int
@@ -179,6 +180,15 @@ def fg(c: int, tau: int, omega_: int, L: float) -> tuple:
     f, g = C.c_double(), C.c_double()
     lib().oracle_fg(c, tau, omega_, L, C.byref(f), C.byref(g))
     return f.value, g.value
+
+
+def fg_batch(counts, tau: int, omega_: int, L: float) -> tuple:
+    """fg of every counter at one (tau, omega, L): two float64 arrays."""
+    c = np.ascontiguousarray(counts, dtype=np.int32)
+    f = np.empty(c.size, dtype=np.float64)
+    g = np.empty(c.size, dtype=np.float64)
+    lib().oracle_fg_batch(c.size, c, tau, omega_, L, f, g)
+    return f, g
 
 
 def check_stop(counts, tau: int, omega_: int, L: float, eps: float) -> bool:

@@ -258,6 +258,13 @@ void oracle_fg(int32_t c, int64_t tau, int64_t omega, double L, double *f_out, d
     *g_out = (L / t) * (ag + sqrt(ag * ag + q));
 }
 
+/* f and g of every counts[k] (k < n) at one (tau, omega, L), as oracle_fg. */
+void oracle_fg_batch(int64_t n, const int32_t *counts, int64_t tau, int64_t omega, double L, double *f,
+                     double *g)
+{
+    for (int64_t k = 0; k < n; ++k) oracle_fg(counts[k], tau, omega, L, &f[k], &g[k]);
+}
+
 /* Returns 1 iff the stopping condition holds on (counts, tau). */
 int oracle_check_stop(int32_t n, const int32_t *counts, int64_t tau, int64_t omega, double L,
                       double eps)
@@ -303,10 +310,15 @@ int oracle_check_stop_v(int32_t n, const int32_t *counts, int64_t tau, int64_t o
 /*     f stays below eps for every L (its limit is b w / (w - t/3)): then    */
 /*     L_f = +inf.  For g the same with ag = 1/3 + w/t (always finite).      */
 /*  4. S(t) = sum_v exp(-L_f(v, t)) + exp(-L_g(v, t)) is the failure budget  */
-/*     that makes every vertex meet the rule at t if b~ = b_p.  t* is found  */
-/*     by bisection on [1, omega] for S(t) <= (1 - beta) delta/2; if the     */
-/*     bisection ends at omega there is no plan and the uniform constants    */
-/*     are kept.                                                             */
+/*     that makes every vertex meet the rule at t if b~ = b_p.  The terms    */
+/*     depend on v only through c1(v) = k, so S is evaluated over the count  */
+/*     histogram h(k) = #{v : c1(v) = k}: the rows with h(k) > 0 in          */
+/*     ascending k, each adding h(k) (exp(-L_f(k)) + exp(-L_g(k))), left to  */
+/*     right in double.  This order is part of the definition: any           */
+/*     implementation that sums in it with the same exp gets the same bits.  */
+/*     t* is found by bisection on [1, omega] for S(t) <= (1 - beta)         */
+/*     delta/2; if the bisection ends at omega there is no plan and the      */
+/*     uniform constants are kept.                                           */
 /*  5. delta_L(v) = (1 - beta) exp(-L_f(v, t*)) + beta delta / (4 n), and    */
 /*     delta_U(v) likewise: a floor share beta = 1/10 of the budget, spread  */
 /*     uniformly, covers vertices whose count grows past the plan.  Then    */
@@ -344,17 +356,22 @@ static double plan_b(int32_t c1, int64_t m1)
     return ((double)c1 + 1.0) / (double)m1;
 }
 
-/* S(t) of step 4, summed over the vertices in increasing id order. */
+/* S(t) of step 4: over the count histogram's nonzero rows in ascending k. */
 double oracle_plan_sum(int32_t n, const int32_t *c1, int64_t m1, int64_t t, int64_t omega,
                        double eps)
 {
+    int64_t *h = calloc((size_t)m1 + 1, sizeof *h);
+    if (!h) return NAN;
+    for (int32_t v = 0; v < n; ++v)
+        if (c1[v] >= 0 && (int64_t)c1[v] <= m1) h[c1[v]] += 1;
     double S = 0.0;
-    for (int32_t v = 0; v < n; ++v) {
+    for (int64_t k = 0; k <= m1; ++k) {
+        if (h[k] == 0) continue;
         double Lf, Lg;
-        oracle_plan_lfg(plan_b(c1[v], m1), t, omega, eps, &Lf, &Lg);
-        S += exp(-Lf);
-        S += exp(-Lg);
+        oracle_plan_lfg(((double)k + 1.0) / (double)m1, t, omega, eps, &Lf, &Lg);
+        S += (double)h[k] * (exp(-Lf) + exp(-Lg));
     }
+    free(h);
     return S;
 }
 

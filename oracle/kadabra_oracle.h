@@ -52,6 +52,9 @@ int32_t oracle_vd_bound(int32_t n, const int32_t *row_ptr, const int32_t *col, c
 int64_t oracle_omega(int32_t vd, double eps, double delta);
 double oracle_log_inv_delta(int32_t n, double delta);
 void oracle_fg(int32_t c, int64_t tau, int64_t omega, double L, double *f, double *g);
+/* oracle_fg over counts[0, n) at one (tau, omega, L) into f[0, n), g[0, n). */
+void oracle_fg_batch(int64_t n, const int32_t *counts, int64_t tau, int64_t omega, double L, double *f,
+                     double *g);
 int oracle_check_stop(int32_t n, const int32_t *counts, int64_t tau, int64_t omega, double L,
                       double eps);
 int oracle_check_stop_v(int32_t n, const int32_t *counts, int64_t tau, int64_t omega,

@@ -203,7 +203,6 @@ struct Params {
     int64_t balance_samples = 0;  // first-phase samples; 0: ceil(omega / 20)
     int64_t fail_alloc = 0;  // test hook
     int32_t level_cap = 0;   // test hook: 0, or a smaller level capacity per side
-    int32_t plan_cache = 0;  // test hook: 0, or fewer histogram rows kept in LDS by the plan search
 };
 
 int set_common_param(Params &p, const char *key, int64_t value, bool *known)
@@ -239,9 +238,6 @@ int set_common_param(Params &p, const char *key, int64_t value, bool *known)
         if (value < 0 || value > kMaxFirstPhase)
             return fail(KADABRA_EINVAL, "balance_samples must be in [0, %lld]", (long long)kMaxFirstPhase);
         p.balance_samples = value;
-    } else if (!strcmp(key, "test_plan_cache_rows")) {
-        if (value < 0 || value > (1 << 20)) return fail(KADABRA_EINVAL, "test_plan_cache_rows must be in [0, 2^20]");
-        p.plan_cache = (int32_t)value;
     } else if (!strcmp(key, "test_fail_alloc")) {
         if (value < 0) return fail(KADABRA_EINVAL, "test_fail_alloc must be >= 0");
         p.fail_alloc = value;
@@ -267,7 +263,6 @@ int get_common_param(const Params &p, const char *key, int64_t *value)
     else if (!strcmp(key, "balance")) *value = p.balance;
     else if (!strcmp(key, "balance_samples")) *value = p.balance_samples;
     else if (!strcmp(key, "test_level_cap")) *value = p.level_cap;
-    else if (!strcmp(key, "test_plan_cache_rows")) *value = p.plan_cache;
     else return 1;
     return 0;
 }
@@ -372,6 +367,73 @@ int gpu_preprocess(GraphData &gd, hipStream_t s)
     return KADABRA_OK;
 }
 
+// Balanced delta_L(v), delta_U(v) (Section 2.3 bounds only their sum over the
+// vertices; this library spends delta/2 on it, the omega cap the other half).
+// From the first phase's count histogram h(k) = #{v : c1(v) = k}, k <= m1:
+//   - planning value b(k) = (k + 1) / m1;
+//   - at a target count t, the largest log(1/delta) with f <= eps (Appendix
+//     B) is L_f = t eps^2 / (q + 2 eps af), af = 1/3 - w/t, q = 2 b w / t,
+//     unbounded when the denominator is <= 0 (f then stays below eps for every
+//     constant); L_g the same with ag = 1/3 + w/t;
+//   - S(t) = sum over the rows with h(k) > 0, ascending k, of
+//     h(k) (exp(-L_f) + exp(-L_g)), added left to right;
+//   - t* = bisection on [1, omega] (midpoint lo + (hi - lo) / 2) for
+//     S(t) <= 0.9 (delta/2) (1 - 1e-6); ending at omega means no plan;
+//   - log(1/delta_L) = -log(0.9 exp(-L_f(t*)) + 0.1 delta / (4 n)), and
+//     log(1/delta_U) with L_g.
+// Evaluated on the host in IEEE double in the order written (no contraction)
+// with the C library's exp and log, so t* and every constant follow from the
+// histogram alone.  Writes lcon[2k], lcon[2k + 1] for k = 0 .. m1 (rows no
+// vertex has keep L) and returns t* (0: no plan, every constant L).
+constexpr double kBalanceFloor = 0.1;  // share of the budget spread evenly
+
+void balance_lfg(double b, double t, double w, double eps, double *lf, double *lg)
+{
+    const double af = 1.0 / 3.0 - w / t;
+    const double ag = 1.0 / 3.0 + w / t;
+    const double q = 2.0 * b * w / t;
+    const double df = q + 2.0 * eps * af;
+    const double dg = q + 2.0 * eps * ag;
+    const double e2 = eps * eps;
+    *lf = (df > 0.0) ? t * e2 / df : HUGE_VAL;
+    *lg = t * e2 / dg;
+}
+
+int64_t balance_plan(const int32_t *hist, int64_t m1, int64_t omega, double eps, double delta, double L, int32_t n,
+                     std::vector<double> *lcon)
+{
+    const double beta = kBalanceFloor;
+    const double target = (1.0 - beta) * (delta / 2.0) * (1.0 - 1e-6);
+    const double w = (double)omega, m = (double)m1;
+    std::vector<int64_t> rows;  // k with h(k) > 0, ascending
+    for (int64_t k = 0; k <= m1; ++k)
+        if (hist[k] > 0) rows.push_back(k);
+    int64_t lo = 1, hi = omega;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        const double t = (double)mid;
+        double S = 0.0;
+        for (const int64_t k : rows) {
+            double lf, lg;
+            balance_lfg(((double)k + 1.0) / m, t, w, eps, &lf, &lg);
+            S += (double)hist[k] * (std::exp(-lf) + std::exp(-lg));
+        }
+        if (S <= target) hi = mid;
+        else lo = mid + 1;
+    }
+    lcon->assign(2 * ((size_t)m1 + 1), L);
+    if (lo >= omega) return 0;
+    const double t = (double)lo;
+    const double floor_share = beta * delta / (4.0 * (double)n);
+    for (const int64_t k : rows) {
+        double lf, lg;
+        balance_lfg(((double)k + 1.0) / m, t, w, eps, &lf, &lg);
+        (*lcon)[2 * (size_t)k] = -std::log((1.0 - beta) * std::exp(-lf) + floor_share);
+        (*lcon)[2 * (size_t)k + 1] = -std::log((1.0 - beta) * std::exp(-lg) + floor_share);
+    }
+    return lo;
+}
+
 // One adaptive run.
 struct Query {
     const GraphData *gd = nullptr;
@@ -409,6 +471,8 @@ struct Query {
     int64_t work[kd::ST_COUNT] = {};
     int64_t work_first[kd::ST_COUNT] = {};  // the first phase's work counters
     int64_t plan_tau = 0;       // planned sample count t* (0: no plan)
+    std::vector<int32_t> h_hist;  // balanced runs: host copies of the count histogram and
+    std::vector<double> h_lcon;   // the constant table (read by the copy to the device)
     double ms_kernels = 0.0;    // sampler launches that did this query's work
     int64_t launches = 0;
     std::chrono::steady_clock::time_point t_submit, t_done;
@@ -868,21 +932,21 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
         HIP_OR_FAIL(kd::launch_sample(team, grid, sa, mapped, stream));
         HIP_OR_FAIL(hipEventRecord(L.e1, stream));
         pend.push_back(std::move(L));
-        // the balanced constants, from the finished first phase, before any check
+        // the balanced constants, from the finished first phase, before any
+        // check: the histograms on the device, the plans on the host (the C
+        // library's exp and log)
         for (Query *q : planned) {
             HIP_OR_FAIL(kd::launch_hist(q->c1, q->gd->n, q->hist(), q->m1, d_ctl + q->cslot, stream));
-            kd::PlanArgs pa{};
-            pa.hist = q->hist();
-            pa.lcon = q->lcon();
-            pa.ctl = d_ctl + q->cslot;
-            pa.m1 = q->m1;
-            pa.omega = q->omega;
-            pa.eps = q->eps;
-            pa.delta = q->delta;
-            pa.L = q->L;
-            pa.n = q->gd->n;
-            pa.cache_rows = p.plan_cache;
-            HIP_OR_FAIL(kd::launch_plan(pa, stream));
+            q->h_hist.resize((size_t)q->m1 + 1);
+            HIP_OR_FAIL(hipMemcpyAsync(q->h_hist.data(), q->hist(), q->h_hist.size() * sizeof(int32_t),
+                                       hipMemcpyDeviceToHost, stream));
+        }
+        if (!planned.empty()) HIP_OR_FAIL(hipStreamSynchronize(stream));
+        for (Query *q : planned) {
+            q->plan_tau = balance_plan(q->h_hist.data(), q->m1, q->omega, q->eps, q->delta, q->L, q->gd->n,
+                                       &q->h_lcon);
+            HIP_OR_FAIL(hipMemcpyAsync(q->lcon(), q->h_lcon.data(), q->h_lcon.size() * sizeof(double),
+                                       hipMemcpyHostToDevice, stream));
         }
         return KADABRA_OK;
     };
@@ -997,7 +1061,6 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
                 q->decision = dec;
                 for (int w = 0; w < kd::ST_COUNT; ++w) q->work[w] = c.stats_total[w];
                 for (int w = 0; w < kd::ST_COUNT; ++w) q->work_first[w] = c.stats[kd::kFirstSet][w];
-                q->plan_tau = c.plan_tau;
                 finished.push_back(q);
             } else {
                 still.push_back(q);

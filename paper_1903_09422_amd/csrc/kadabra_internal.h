@@ -43,7 +43,6 @@ struct Control {
     int64_t stats[kMaxSets + 1][ST_COUNT];  // work counters of epochs in flight, by set;
                                             // [kFirstSet]: the first phase (never merged)
     int64_t stats_total[ST_COUNT];   // work counters of merged epochs
-    int64_t plan_tau;                // balanced runs: planned sample count t* (0 = no plan)
     int64_t phase_cycles[8];         // per-phase cycles (phase-timer builds only)
 };
 
@@ -131,23 +130,12 @@ struct MergeArgs {
 
 // Balancing of delta_L(v), delta_U(v) from the first-phase counters c1:
 // hist[k] = #{v : c1[v] = k} (hist zeroed beforehand, m1 + 1 entries; a
-// counter above m1 cannot occur and is reported as device error 4), then
-// one workgroup finds t* and writes lcon[2k], lcon[2k + 1] for k = 0 .. m1
-// and ctl->plan_tau.
-struct PlanArgs {
-    const int32_t *hist;
-    double *lcon;
-    Control *ctl;
-    int64_t m1, omega;
-    double eps, delta, L;
-    int32_t n;
-    int32_t cache_rows;   // test hook: > 0 caps the histogram rows the search keeps in LDS
-};
+// counter above m1 cannot occur and is reported as device error 4).  The
+// host then plans t* and the constant table lcon from the histogram.
 
 // mapped: some query of the launch is on a relabelled graph
 hipError_t launch_sample(int team, int slots, const SampleArgs &a, bool mapped, hipStream_t s);
 hipError_t launch_hist(const int32_t *c1, int32_t n, int32_t *hist, int64_t m1, Control *ctl, hipStream_t s);
-hipError_t launch_plan(const PlanArgs &a, hipStream_t s);
 hipError_t launch_merge_check(const MergeArgs &a, hipStream_t s);
 int32_t merge_blocks_for(int32_t n);
 hipError_t launch_scores(const int32_t *counts, double *scores, int32_t n, int64_t tau,

@@ -76,10 +76,25 @@ def test_batch_rerun_and_clear():
     h.close()
 
 
-def test_batch_pool_equals_single_runs():
-    """The 64-graph batched workload: each query in the mix equals the same
-    query run alone; the smaller ones are also checked against the oracle."""
+def same_as_stored(got, ref):
+    """A result against a stored oracle result (tests/golden/oracle_runs.json,
+    written by make_oracle_golden.py from the oracle alone): tau, every counter
+    (sha256 and sampled values) and every work counter."""
+    assert got.tau == ref["tau"]
+    assert hashlib.sha256(got.counts.astype("<i4").tobytes()).hexdigest() == ref["counts_sha256"]
+    assert got.counts[ref["sample_idx"]].tolist() == ref["sample_counts"]
+    for k in WORK_KEYS:
+        assert got.stats[k] == ref["stats"][k], k
+    assert got.stats["omega"] == ref["stats"]["omega"]
+
+
+def test_batch_pool_equals_oracle_and_single_runs():
+    """The 64-graph batched workload: every query in the mix equals the
+    oracle's stored result and the same query run alone."""
     pool = G.batch_pool()
+    with open(os.path.join(GOLDEN, "oracle_runs.json")) as f:
+        stored = json.load(f)["batch64"]
+    assert len(stored) == len(pool) == 64
     print("case batch pool (64 graphs)", flush=True)
     handles = [Graph.from_csr(g) for g, *_ in pool]
     with Batch() as b:
@@ -87,13 +102,14 @@ def test_batch_pool_equals_single_runs():
             b.add(h, eps, delta, seed, n_check)
         b.run()
         for k, (h, (g, eps, delta, n_check, seed)) in enumerate(zip(handles, pool)):
+            ref = stored[k]
+            assert (ref["graph_sha256"], ref["eps"], ref["seed"], ref["check_interval"]) == \
+                (g.sha256(), eps, seed, n_check)
+            mixed = b.result(k)
+            same_as_stored(mixed, ref)
             h.set_param("check_interval", n_check)
             h.run(eps, delta, seed)
-            alone = h.result()
-            mixed = b.result(k)
-            _same(mixed, alone)
-            if g.n <= 5000 and eps >= 0.02:
-                _same(mixed, oracle.run(g, eps, delta, seed, n_check))
+            _same(h.result(), mixed)
     for h in handles:
         h.close()
 

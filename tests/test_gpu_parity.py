@@ -188,16 +188,23 @@ def test_workload_against_stored_oracle(name):
 
 
 def test_mapping_does_not_change_results():
+    """Every mapping knob on R-MAT-18 gives the oracle's stored result."""
     g, eps, delta, n_check = G.workload("rmat18")
+    with open(os.path.join(GOLDEN, "oracle_runs.json")) as f:
+        ref = json.load(f)["rmat18"]
     print("case rmat18 mappings", flush=True)
-    base = gpu_run(g, eps, delta, 5, n_check, team=256)
+    base = gpu_run(g, eps, delta, ref["seed"], n_check, team=256)
+    assert base.tau == ref["tau"]
+    assert hashlib.sha256(base.counts.astype("<i4").tobytes()).hexdigest() == ref["counts_sha256"]
+    for k in WORK_KEYS:
+        assert base.stats[k] == ref["stats"][k], k
     for params in ({"team": 64}, {"team": 128}, {"team": 512}, {"team": 256, "slots": 37}, {"team": 64, "slots": 1000},
                    {"team": 128, "slots": 2048}, {"epochs_per_launch": 1}, {"epochs_per_launch": 3},
                    {"epochs_per_launch": 4, "overlap": 0},
                    {"frames": 8}, {"overlap": 0}, {"team": 64, "frames": 3, "overlap": 0},
                    {"probe_min": 0}, {"probe_min": 1 << 40}, {"team": 64, "probe_min": 0}):
         print("  mapping", params, flush=True)
-        got = gpu_run(g, eps, delta, 5, n_check, **params)
+        got = gpu_run(g, eps, delta, ref["seed"], n_check, **params)
         assert got.tau == base.tau and np.array_equal(got.counts, base.counts), params
         for k in WORK_KEYS:
             assert got.stats[k] == base.stats[k], (params, k)
@@ -218,17 +225,30 @@ def test_repeated_runs_on_one_handle():
 
 
 def test_stop_functions_bitwise():
-    """The device f, g (IEEE double, no contraction) equal the oracle's."""
+    """The device f, g (IEEE double, no contraction) equal the oracle's bit for
+    bit on 10^7 inputs: 40 draws of (omega, tau, L), omega log-uniform below
+    2^31, tau = omega, tau = 1 or uniform, L = log(4n/delta) over n < 2^23,
+    each with 250,000 counters (half uniform in [0, tau], half in the small
+    range [0, min(tau, 64)] where most counters lie, and both ends)."""
     rng = np.random.default_rng(0)
-    for _ in range(20):
-        omega = int(rng.integers(1, 2**31 - 1))
-        tau = int(rng.integers(1, omega + 1))
+    total = 0
+    for call in range(40):
+        omega = min(int(np.exp(rng.uniform(0.0, np.log(2.0**31 - 2)))) + 1, 2**31 - 1)
+        tau = omega if call % 10 == 0 else (1 if call % 10 == 1 else int(rng.integers(1, omega + 1)))
         L = float(np.log(4 * int(rng.integers(2, 2**23)) / rng.uniform(0.001, 0.999)))
-        counts = rng.integers(0, tau + 1, size=5000).astype(np.int32)
+        m = 250_000
+        counts = np.concatenate([rng.integers(0, tau + 1, size=m // 2),
+                                 rng.integers(0, min(tau, 64) + 1, size=m - m // 2)]).astype(np.int32)
+        counts[:2] = (0, tau)
         f, g = eval_stop_fg(counts, tau, omega, L)
-        for k in range(0, 5000, 97):
-            fo, go = oracle.fg(int(counts[k]), tau, omega, L)
-            assert f[k] == fo and g[k] == go, (counts[k], tau, omega, L)
+        fo, go = oracle.fg_batch(counts, tau, omega, L)
+        for got, want, name in ((f, fo, "f"), (g, go, "g")):
+            if not np.array_equal(got.view(np.uint64), want.view(np.uint64)):
+                k = int(np.flatnonzero(got.view(np.uint64) != want.view(np.uint64))[0])
+                raise AssertionError(f"{name} differs at c={counts[k]} tau={tau} omega={omega} L={L!r}: "
+                                     f"device {got[k]!r} oracle {want[k]!r}")
+        total += m
+    assert total == 10**7
 
 
 def test_errors_and_state():

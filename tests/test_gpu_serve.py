@@ -2,6 +2,9 @@
 running launches at the next round boundary; each result equals the oracle's
 and the query's own single run, bit for bit, whatever else was in flight.
 Admission respects the device-memory budget."""
+import hashlib
+import json
+import os
 import threading
 import time
 
@@ -15,6 +18,7 @@ from paper_1903_09422_amd import graphs as G
 pytestmark = pytest.mark.gpu
 
 WORK_KEYS = ("v_exp", "e_scan", "e_bt", "path_interior", "disconnected")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 MIX = [
     (G.erdos_renyi(600, 6.0, seed=11), 0.05, 128),
@@ -230,3 +234,44 @@ def test_serve_concurrent_reads_and_release():
         with pytest.raises(KadabraError) as e:
             srv.result(t)
         assert e.value.status == _lib.EINVAL
+
+
+def test_serve_workload_graphs_equal_oracle():
+    """The served workload's graphs at their serving settings, submitted
+    together: R-MAT scale 22 at eps 0.05 and 0.01, the perturbed 1024 x 1024
+    grid and R-MAT scale 18 at eps 0.01, and eight queries of the 64-graph
+    pool.  Every result equals the oracle's stored result (tau, every counter
+    by sha256 and sampled values, every work counter)."""
+    with open(os.path.join(GOLDEN, "oracle_runs.json")) as f:
+        stored = json.load(f)
+    print("case serve workload graphs: building R-MAT scale 22", flush=True)
+    rmat22 = G.rmat(22, 16, seed=1)
+    assert rmat22.sha256() == stored["rmat22_eps0.01"]["graph_sha256"]
+    print("case serve workload graphs: building the pool, grid and R-MAT scale 18", flush=True)
+    pool = G.batch_pool()
+    grid, _, _, _ = G.workload("pgrid1024")
+    r18, _, _, _ = G.workload("rmat18")
+    picks = [3, 11, 24, 30, 33, 42, 50, 63]
+    graphs = [rmat22, grid, r18] + [pool[k][0] for k in picks]
+    handles = [Graph.from_csr(g) for g in graphs]
+    jobs = [(0, stored["rmat22_eps0.01"]), (1, stored["pgrid1024"]), (0, stored["rmat22_eps0.05"]),
+            (2, stored["rmat18"])]
+    for j, k in enumerate(picks):
+        jobs.append((3 + j, stored["batch64"][k]))
+    print("case serve workload graphs: serving", len(jobs), "queries", flush=True)
+    with Server(handles) as srv:
+        tickets = [srv.submit(gi, ref["eps"], ref["delta"], ref["seed"], ref["check_interval"])
+                   for gi, ref in jobs]
+        for t, (gi, ref) in zip(tickets, jobs):
+            assert srv.wait(t, timeout=120.0)
+            got, _ = srv.result(t, gi, scores=False)
+            assert graphs[gi].sha256() == ref["graph_sha256"]
+            assert got.tau == ref["tau"], gi
+            assert hashlib.sha256(got.counts.astype("<i4").tobytes()).hexdigest() == ref["counts_sha256"], gi
+            assert got.counts[ref["sample_idx"]].tolist() == ref["sample_counts"]
+            for k in WORK_KEYS:
+                assert got.stats[k] == ref["stats"][k], (gi, k)
+            srv.release(t)
+            print("  served graph", gi, "tau", got.tau, "equals the oracle", flush=True)
+    for h in handles:
+        h.close()
