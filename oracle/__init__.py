@@ -14,12 +14,27 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "kadabra_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB names another build of the oracle (for example one with
+# sanitizers); by default the in-tree build is loaded.
+_LIB = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off", "-fPIC", "-shared"]
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no fast-math, no contraction)."""
+SAN_LIB = os.path.join(os.path.dirname(_HERE), "_build", "liboracle_san.so")
+SAN_FLAGS = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+             "-fno-omit-frame-pointer"]
+
+
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (no fast-math, no contraction).  With
+    sanitize, an AddressSanitizer + UndefinedBehaviorSanitizer build goes to
+    _build/liboracle_san.so (load it with ORACLE_LIB and gcc's libasan and
+    libubsan preloaded)."""
+    if sanitize:
+        os.makedirs(os.path.dirname(SAN_LIB), exist_ok=True)
+        flags = [f for f in CFLAGS if f != "-O2"] + SAN_FLAGS
+        subprocess.check_call(["gcc", *flags, _SRC, "-o", SAN_LIB, "-lm"])
+        return SAN_LIB
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])

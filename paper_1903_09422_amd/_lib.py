@@ -9,7 +9,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libkadabra.so")
+# KADABRA_LIB names another build of the same library (for example one with
+# host-side sanitizers); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("KADABRA_LIB") or os.path.join(HERE, "libkadabra.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ERANGE, ECANCELED = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE",

@@ -23,17 +23,30 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source into libkadabra.so (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-x", "hip", *SOURCES, "-o", tmp]
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer (the device code is
+# built as usual): every sanitizer flag applies to the host pass only.
+SAN_LIB = os.path.join(ROOT, "_build", "libkadabra_san.so")
+SAN_FLAGS = ["-O1", "-g"] + [x for f in ("-fsanitize=address", "-fsanitize=undefined",
+                                         "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer")
+                             for x in ("-Xarch_host", f)]
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Compile every source into libkadabra.so (always recompiles).  With
+    sanitize, a host-sanitized copy goes to _build/libkadabra_san.so instead
+    (load it with KADABRA_LIB and the clang ASan runtime preloaded)."""
+    out = SAN_LIB if sanitize else LIB
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp"
+    flags = [f for f in FLAGS if f != "-O3"] + SAN_FLAGS if sanitize else FLAGS
+    cmd = [HIPCC, *flags, "-x", "hip", *SOURCES, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed ({res.returncode}):\n{res.stderr}")
     if verbose and res.stderr:
         print(res.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

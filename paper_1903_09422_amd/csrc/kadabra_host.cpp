@@ -1569,11 +1569,7 @@ StaticLayout static_layout(int64_t n, int32_t lcap, int64_t slots)
 
 }  // namespace
 
-extern "C" {
-
-const char *kadabra_last_error(void) { return g_last_error.c_str(); }
-
-int kadabra_version(void) { return 10100; }
+namespace {
 
 // Graphs whose vertex-diameter bound reaches this are relabelled for locality.
 constexpr int32_t kRelabelMinVd = 64;
@@ -1697,6 +1693,14 @@ int relabel_for_locality(GraphData &gd, const int32_t *row_ptr, const int32_t *c
     gd.h_perm = std::move(perm);
     return KADABRA_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+const char *kadabra_last_error(void) { return g_last_error.c_str(); }
+
+int kadabra_version(void) { return 10100; }
 
 int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr, const int32_t *col_idx,
                          kadabra_graph **out)
