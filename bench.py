@@ -25,18 +25,58 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
-# Algorithmic bytes per unit of work counted by the sampler (a lower bound:
-# what any implementation of the method must read per unit):
-BYTES_PER = {
-    "v_exp": 28,          # expanded frontier vertex: row_ptr pair 8 + sigma 16 + list entry 4
-    "e_scan": 12,         # scanned arc: column index 4 + the neighbour's distance pair 8
-    "e_bt": 12,           # arc scanned when backtracking: column index 4 + distance pair 8
-    "path_interior": 4,   # counter increment
-}
+# Algorithmic bytes per unit of work.  The roofline's `achieved` uses the
+# per-unit figures of the method's traffic model over the oracle's counters of
+# the same samples (the oracle counts every unit; its counters for the stored
+# workloads are in tests/golden/oracle_runs.json):
+#   8 V_exp   row_ptr pair of an expanded frontier vertex
+#   8 E_scan  column index 4 + the target's distance from the expanding side 4
+#   16 V_new  the other side's distance (meeting test) 4 + distance and sigma
+#             written 12, for every newly reached vertex
+#   8 E_pred  sigma read per predecessor arc
+#   12 E_bt   column index and distance per arc of a backtracked row
+#   12 per path interior vertex: its row_ptr pair 8 (|backtracked| taken as
+#             the interior count) + the counter increment 4
+MODEL_BYTES = {"v_exp": 8, "e_scan": 8, "v_new": 16, "e_pred": 8, "e_bt": 12, "path_interior": 12}
+# The same terms for this sampler, from its own counters: sigma is read once
+# per frontier vertex (the push form, 8 per V_exp instead of 8 per E_pred),
+# and only the new vertices actually written are charged 16 -- a meeting
+# level expanded with the meeting probe writes only the meeting set.
+PROBE_MODEL_BYTES = {"v_exp": 16, "e_scan": 8, "v_written": 16, "e_bt": 12, "path_interior": 12}
 
 
-def algorithmic_bytes(stats: dict) -> int:
-    return sum(BYTES_PER[k] * int(stats[k]) for k in BYTES_PER)
+def model_bytes(stats: dict, per_unit: dict) -> int:
+    return sum(per_unit[k] * int(stats[k]) for k in per_unit)
+
+
+def stored_oracle(name: str):
+    """The oracle's stored result for a named workload (or the list of the
+    batched pool's), written by tests/golden/make_oracle_golden.py."""
+    path = os.path.join(ROOT, "tests", "golden", "oracle_runs.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f).get(name)
+
+
+def copy_bandwidth_gbs(nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """Device-to-device copy rate on this GPU (bytes read + written per s)."""
+    import torch
+
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes * reps / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(g, eps, delta, seed, n_check, min_seconds, max_repeats):
@@ -82,6 +122,9 @@ def main() -> int:
                     help="CPU oracle leg: repeat complete runs until this much time is timed")
     ap.add_argument("--cpu-repeats", type=int, default=50, help="CPU oracle leg: at most this many runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--legs", default="pgrid1024,er4096,batch64,serve",
+                    help="with the default workload: the other workloads measured in the same run "
+                         "(comma-separated; empty: none), reported under `workloads`")
     ap.add_argument("--traffic-json", default=None,
                     help="HBM bytes per sampler launch from rocprofv3 counters (default: "
                          "profiles/sample_kernel_<workload>_traffic.json)")
@@ -110,15 +153,48 @@ def main() -> int:
         return 2
 
     if args.workload == "batch64":
-        return bench_batch(args)
+        out = bench_batch(args, args.steps, args.warmup, autotune=True)
+        print(json.dumps(out))
+        return 0
     if args.workload == "serve":
-        return bench_serve(args)
+        out = bench_serve(args, (0.5, 0.8, 1.0))
+        print(json.dumps(out))
+        return 0
 
+    copy_gbs = copy_bandwidth_gbs()
+    out = measure_single(args.workload, args, args.steps, args.warmup, args.balanced_steps,
+                         not args.no_cpu, copy_gbs)
+    legs = [w for w in args.legs.split(",") if w] if args.workload == "rmat18" else []
+    if legs:
+        out["workloads"] = {}
+    for w in legs:
+        print(f"bench: leg {w}", file=sys.stderr, flush=True)
+        if w == "batch64":
+            leg = bench_batch(args, 3, 1, autotune=True)
+        elif w == "serve":
+            leg = bench_serve(args, (1.0,))
+        else:
+            leg = measure_single(w, args, 5 if w == "pgrid1024" else args.steps, 1, 0, False, copy_gbs)
+        out["workloads"][w] = _leg_summary(leg)
+    print(json.dumps(out))
+    return 0
+
+
+def _leg_summary(leg: dict) -> dict:
+    keep = ("value", "unit", "ms_per_step", "config", "traversed_edges_per_s", "query_latency_ms",
+            "roofline", "serial_samples_per_s", "speedup_vs_serial", "autotuned", "saturated",
+            "speedup_vs_one_at_a_time", "poisson", "dtype")
+    return {k: leg[k] for k in keep if k in leg}
+
+
+def measure_single(workload, args, steps, warmup, balanced_steps, with_cpu, copy_gbs) -> dict:
+    """One query of a named workload, run `steps` times (one step = one
+    complete adaptive run plus the device scores)."""
     import torch
 
     from paper_1903_09422_amd import Graph, graphs
 
-    g, eps, delta, n_check = graphs.workload(args.workload)
+    g, eps, delta, n_check = graphs.workload(workload)
     dev = Graph.from_csr(g)  # uploads the CSR: inputs resident before timing
     dev.set_param("check_interval", n_check)
     dev.set_param("team", args.team)
@@ -136,12 +212,12 @@ def main() -> int:
         dev.result_device(scores=scores)
         return dev.stats()
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    lat, samples, escan, kern_ms, kern_bytes, launches = [], 0, 0, 0.0, 0, 0
+    lat, samples, escan, kern_ms, probe_bytes, launches = [], 0, 0, 0.0, 0, 0
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         ts = time.perf_counter()
         st = step()
         stream.synchronize()
@@ -150,35 +226,46 @@ def main() -> int:
         escan += st["e_scan"]
         kern_ms += st["ms_sample_kernels"]
         launches += st["sample_launches"]
-        kern_bytes += algorithmic_bytes(st)
+        probe_bytes += model_bytes(st, PROBE_MODEL_BYTES)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
-    achieved = kern_bytes / (kern_ms * 1e-3) / 1e9  # GB/s over the sampler launches
+    avg_launch_ms = kern_ms / max(launches, 1)
+    # the method's bytes for these samples, from the oracle's counters of the
+    # same query (stored for seed 1; every shared counter equals the GPU's)
+    ref = stored_oracle(workload)
+    model = None
+    if ref and ref["seed"] == args.seed and ref["graph_sha256"] == g.sha256() and ref["tau"] == st["tau"] \
+            and all(int(ref["stats"][k]) == int(st[k]) for k in ("v_exp", "e_scan", "e_bt", "path_interior")):
+        model = model_bytes(ref["stats"], MODEL_BYTES) / max(st["sample_launches"], 1)
+    probe_per_launch = probe_bytes / max(launches, 1)
+    per_launch = model if model is not None else probe_per_launch
+    achieved = per_launch / (avg_launch_ms * 1e-3) / 1e9
+    probe_achieved = probe_per_launch / (avg_launch_ms * 1e-3) / 1e9
     traffic = None
-    tj_path = args.traffic_json or os.path.join(ROOT, "profiles",
-                                                f"sample_kernel_{args.workload}_traffic.json")
+    tj_path = args.traffic_json or os.path.join(ROOT, "profiles", f"sample_kernel_{workload}_traffic.json")
     if os.path.exists(tj_path):
         with open(tj_path) as f:
             tj = json.load(f)
-        if tj.get("workload") == args.workload and tj.get("kernel_source_sha") == _kernel_sha():
+        if tj.get("workload") == workload and tj.get("kernel_source_sha") == _kernel_sha():
             traffic = tj.get("hbm_bytes_per_launch")
-    traffic_gbs = None if traffic is None else traffic / (kern_ms / max(launches, 1) * 1e-3) / 1e9
+    traffic_gbs = None if traffic is None else traffic / (avg_launch_ms * 1e-3) / 1e9
     out = {
-        "metric": "samples/s (KADABRA adaptive sampling, eps=0.01)",
+        "metric": "samples/s (KADABRA adaptive sampling, eps=0.01)" if eps == 0.01 else
+                  f"samples/s (KADABRA adaptive sampling, eps={eps})",
         "value": samples / dt,
         "unit": "samples/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": dt * 1e3 / args.steps,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": dt * 1e3 / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
         "config": {
-            "workload": _describe(args.workload, g, eps, delta, n_check, args.seed),
+            "workload": _describe(workload, g, eps, delta, n_check, args.seed),
             "tau": int(st["tau"]),
             "omega": int(st["omega"]),
             "mapping": {"team": dev.get_param("last_team"), "slots": dev.get_param("last_slots"),
@@ -198,31 +285,37 @@ def main() -> int:
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "traffic_gbs": traffic_gbs,
-            "avg_launch_ms": kern_ms / max(launches, 1),
-            "algorithmic_bytes_per_launch": kern_bytes / max(launches, 1),
+            "avg_launch_ms": avg_launch_ms,
+            "algorithmic_bytes_per_launch": per_launch,
+            "model": ("8 V_exp + 8 E_scan + 16 V_new + 8 E_pred + 12 E_bt + 12 interior, oracle counters"
+                      if model is not None else "push-form model (no stored oracle counters for this query)"),
+            "probe_model": {"bytes_per_launch": probe_per_launch, "achieved": probe_achieved,
+                            "frac": probe_achieved / HBM_PEAK_GBS,
+                            "terms": "16 V_exp + 8 E_scan + 16 V_written + 12 E_bt + 12 interior"},
+            "copy_gbs": copy_gbs,
+            "frac_of_copy": achieved / copy_gbs,
         },
     }
-    if args.balanced_steps > 0:
-        out["balanced"] = balanced_leg(dev, step, stream, args, dt * 1e3 / args.steps)
-    if not args.no_cpu:
+    if balanced_steps > 0:
+        out["balanced"] = balanced_leg(dev, step, stream, balanced_steps, dt * 1e3 / steps)
+    if with_cpu:
         out["cpu_baseline"] = cpu_baseline(g, eps, delta, args.seed, n_check, args.cpu_seconds,
                                            args.cpu_repeats)
     dev.close()
-    print(json.dumps(out))
-    return 0
+    return out
 
 
-def balanced_leg(dev, step, stream, args, uniform_ms):
+def balanced_leg(dev, step, stream, nsteps, uniform_ms):
     """The same query with balanced delta_L(v), delta_U(v): time per query
     (first phase, plan and adaptive loop) beside the uniform constants'."""
     dev.set_param("balance", 1)
     step()
     stream.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.balanced_steps):
+    for _ in range(nsteps):
         st = step()
         stream.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / args.balanced_steps
+    ms = (time.perf_counter() - t0) * 1e3 / nsteps
     dev.set_param("balance", 0)
     drawn = int(st["tau"] + st["first_samples"])
     return {"ms_per_query": ms, "uniform_ms_per_query": uniform_ms, "speedup": uniform_ms / ms,
@@ -230,11 +323,12 @@ def balanced_leg(dev, step, stream, args, uniform_ms):
             "plan_tau": int(st["plan_tau"]), "samples_per_s": drawn / (ms * 1e-3)}
 
 
-def bench_batch(args) -> int:
+def bench_batch(args, steps, warmup, autotune=False) -> dict:
     """The batched workload: 64 queries (32 R-MAT of scales 12-16, 32 random
     hyperbolic graphs of 2^14-2^17 vertices; eps from {0.05, 0.02, 0.01}),
     run one after another through Graph.run and together through one Batch,
-    on the same GPU.  value = samples/s of the batched form."""
+    on the same GPU (with autotune, the batch's mapping is picked by the
+    library's autotuner first).  value = samples/s of the batched form."""
     import torch
 
     from paper_1903_09422_amd import Batch, Graph, graphs
@@ -251,6 +345,7 @@ def bench_batch(args) -> int:
     batch.set_param("epochs_per_launch", args.epochs_per_launch)
     for h, (g, eps, delta, n_check, seed) in zip(handles, pool):
         batch.add(h, eps, delta, seed, n_check)
+    tuned = batch.autotune(2048) if autotune else None
 
     def serial():
         tot = 0
@@ -263,17 +358,17 @@ def bench_batch(args) -> int:
         batch.run()
         return sum(batch.stats(k)["tau"] for k in range(len(pool)))
 
-    for _ in range(max(args.warmup, 1)):
+    for _ in range(max(warmup, 1)):
         serial()
         batched()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s_serial = sum(serial() for _ in range(args.steps))
+    s_serial = sum(serial() for _ in range(steps))
     t_serial = time.perf_counter() - t0
     lat = []
     t0 = time.perf_counter()
     s_batch = 0
-    for _ in range(args.steps):
+    for _ in range(steps):
         ts = time.perf_counter()
         s_batch += batched()
         lat.append((time.perf_counter() - ts) * 1e3)
@@ -286,22 +381,22 @@ def bench_batch(args) -> int:
         batched()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             s_bal = batched()
-        t_bal = (time.perf_counter() - t0) / args.steps
+        t_bal = (time.perf_counter() - t0) / steps
         first = sum(batch.stats(k)["first_samples"] for k in range(len(pool)))
         batch.set_param("balance", 0)
-        balanced = {"ms_per_batch": t_bal * 1e3, "uniform_ms_per_batch": t_batch * 1e3 / args.steps,
-                    "speedup": (t_batch / args.steps) / t_bal, "samples": s_bal,
-                    "first_phase_samples": first, "uniform_samples": s_batch // args.steps}
+        balanced = {"ms_per_batch": t_bal * 1e3, "uniform_ms_per_batch": t_batch * 1e3 / steps,
+                    "speedup": (t_batch / steps) / t_bal, "samples": s_bal,
+                    "first_phase_samples": first, "uniform_samples": s_batch // steps}
     out = {
         "metric": "samples/s (KADABRA adaptive sampling, 64-query batch)",
         "value": s_batch / t_batch,
         "unit": "samples/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": t_batch * 1e3 / args.steps,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": t_batch * 1e3 / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -311,11 +406,14 @@ def bench_batch(args) -> int:
                                "threshold random hyperbolic graphs (n = 2^(14 + k mod 4), mean "
                                "degree 10, exponent 2.8); eps from {0.05, 0.02, 0.01}, delta 0.1, "
                                "checks every 1024 samples",
-                   "queries": len(pool), "samples_per_step": s_batch // args.steps,
+                   "queries": len(pool), "samples_per_step": s_batch // steps,
                    "mapping": {"team": batch.get_param("last_team"),
-                               "slots": batch.get_param("last_slots")}},
+                               "slots": batch.get_param("last_slots"),
+                               "epochs_per_launch": batch.get_param("epochs_per_launch"),
+                               "probe_min": batch.get_param("probe_min")}},
+        "autotuned": tuned is not None,
         "serial_samples_per_s": s_serial / t_serial,
-        "serial_ms_per_step": t_serial * 1e3 / args.steps,
+        "serial_ms_per_step": t_serial * 1e3 / steps,
         "speedup_vs_serial": (s_batch / t_batch) / (s_serial / t_serial),
         "batch_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
     }
@@ -324,11 +422,10 @@ def bench_batch(args) -> int:
     batch.close()
     for h in handles:
         h.close()
-    print(json.dumps(out))
-    return 0
+    return out
 
 
-def bench_serve(args) -> int:
+def bench_serve(args, loads) -> dict:
     """Serving: a seeded stream of queries (graph drawn uniformly from the
     64-graph pool, the perturbed 1024 x 1024 grid and R-MAT scale 22; eps from
     {0.05, 0.01}, delta 0.1, checks every 16384 samples) against resident
@@ -393,7 +490,7 @@ def bench_serve(args) -> int:
                       "peak_active": info["peak_active"]}
         print(f"serve: {name} saturated {tot / span:.4g} samples/s", file=sys.stderr, flush=True)
         cap = legs["one_at_a_time"]["queries_per_s"]
-        for f in (0.5, 0.8, 1.0):
+        for f in loads:
             t2, span2, inf2 = replay(srv, f * cap)
             assert t2 == tot
             out_rates.setdefault(f"{f:.1f}x", {"arrivals_per_s": f * cap})[name] = {
@@ -428,8 +525,7 @@ def bench_serve(args) -> int:
     }
     for h in handles:
         h.close()
-    print(json.dumps(out))
-    return 0
+    return out
 
 
 COPY_BYTES = 1 << 30

@@ -70,6 +70,12 @@ typedef struct {
     int64_t first_e_bt;
     int64_t first_path_interior;
     int64_t first_disconnected;
+    /* new vertices the level expansions wrote (distance code, sigma, list
+     * entry): every level in full, except that a meeting level expanded with
+     * the meeting probe writes only the meeting set.  Unlike the counters
+     * above it depends on the mapping ("probe_min"); it feeds the roofline's
+     * byte model. */
+    int64_t v_written;
 } kadabra_stats;
 
 /*
@@ -246,12 +252,13 @@ int kadabra_eval_stop_fg(int32_t n, const int32_t *counts, int64_t tau, int64_t 
                          double *f, double *g);
 
 /*
- * Autotuner.  Times a fixed set of mapping candidates (workgroup or
- * wavefront per sample, the number of samples in flight, the meeting probe on
- * or off) on the first trial_samples samples of this graph's query (eps,
- * delta; a fixed calibration seed; no stop checks) and keeps the fastest in
- * the handle's parameters ("team", "slots", "probe_min").  Results never
- * depend on these parameters.  Errors: EINVAL, ERANGE, ENOMEM, EDEVICE.
+ * Autotuner.  Times a fixed set of mapping candidates (one, two or four
+ * wavefronts per sample, the number of samples in flight, the meeting probe
+ * on or off), then the epochs per launch (1, 2, 4) for the best of them, on
+ * the first trial_samples samples of this graph's query (eps, delta; a fixed
+ * calibration seed; no stop checks) and keeps the fastest in the handle's
+ * parameters ("team", "slots", "probe_min", "epochs_per_launch").  Results
+ * never depend on these parameters.  Errors: EINVAL, ERANGE, ENOMEM, EDEVICE.
  */
 int kadabra_autotune(kadabra_graph *g, double eps, double delta, int64_t trial_samples);
 

@@ -112,10 +112,10 @@ class Graph:
         return LL, LU, c1
 
     def autotune(self, eps: float, delta: float, trial_samples: int = 8192) -> dict:
-        """Pick the fastest mapping (team, slots, probe) on a trial prefix;
+        """Pick the fastest mapping (team, slots, probe, epochs per launch) on a trial prefix;
         results never depend on it.  Returns the chosen parameters."""
         check(lib().kadabra_autotune(self._h, float(eps), float(delta), int(trial_samples)))
-        return {k: self.get_param(k) for k in ("team", "slots", "probe_min")}
+        return {k: self.get_param(k) for k in ("team", "slots", "probe_min", "epochs_per_launch")}
 
     def stats(self) -> dict:
         st = Stats()
@@ -188,7 +188,7 @@ class Batch:
 
     def autotune(self, trial_samples: int = 4096) -> dict:
         check(lib().kadabra_batch_autotune(self._h, int(trial_samples)))
-        return {k: self.get_param(k) for k in ("team", "slots", "probe_min")}
+        return {k: self.get_param(k) for k in ("team", "slots", "probe_min", "epochs_per_launch")}
 
     def result(self, index: int) -> RunResult:
         if not 0 <= index < len(self._graphs):  # let the library report the bad index

@@ -47,7 +47,8 @@ class Stats(C.Structure):
         ("log_inv_delta", C.c_double), ("ms_sampling", C.c_double), ("ms_total", C.c_double),
         ("ms_sample_kernels", C.c_double), ("sample_launches", C.c_int64)] + [
         (k, C.c_int64) for k in ("first_samples", "plan_tau", "first_v_exp", "first_e_scan",
-                                 "first_e_bt", "first_path_interior", "first_disconnected")]
+                                 "first_e_bt", "first_path_interior", "first_disconnected",
+                                 "v_written")]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

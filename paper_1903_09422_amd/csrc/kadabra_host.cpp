@@ -1306,6 +1306,7 @@ void fill_stats(const Query &q, double ms_total, kadabra_stats *stats)
     stats->e_bt = q.work[kd::ST_EBT];
     stats->path_interior = q.work[kd::ST_INTERIOR];
     stats->disconnected = q.work[kd::ST_DISCONN];
+    stats->v_written = q.work[kd::ST_VMAT];
     stats->log_inv_delta = q.L;
     stats->ms_sampling = q.ms_kernels;
     stats->ms_total = ms_total;
@@ -1344,40 +1345,48 @@ int ensure_graph_query(kadabra_graph *g, double eps, double delta, uint64_t seed
 }
 
 // Trial-times mapping candidates on the first trial_samples samples of every
-// query (no stop checks) and keeps the fastest in *p.  Results never depend on
-// the mapping, so the choice cannot change any output.
+// query (no stop checks) and keeps the fastest in *p: the team (one, two or
+// four wavefronts per sample), the samples in flight, the meeting probe on or
+// off, then the epochs per launch for the best of those.  Results never depend
+// on the mapping, so the choice cannot change any output.
 int autotune(Runner &R, std::vector<Query *> &qs, Params &p, int64_t trial_samples)
 {
     struct Cand {
         int team;
         int64_t slots_mul2;  // slots = auto * mul2 / 2
         int64_t probe;
+        int epochs;          // 0: keep
     };
-    const Cand cands[] = {{256, 2, -1}, {256, 4, -1}, {256, 1, -1}, {64, 2, -1}, {64, 4, -1},
-                          {256, 2, (int64_t)1 << 62}, {64, 4, (int64_t)1 << 62}};
+    const Cand cands[] = {{256, 2, -1, 0}, {256, 4, -1, 0}, {256, 1, -1, 0}, {128, 2, -1, 0}, {128, 1, -1, 0},
+                          {64, 2, -1, 0},  {64, 4, -1, 0},  {256, 2, (int64_t)1 << 62, 0},
+                          {64, 4, (int64_t)1 << 62, 0}};
     const Params base = p;
     double best = 1e300;
     Params best_p = p;
-    for (const Cand &c : cands) {
-        Params t = base;
-        t.team = c.team;
-        t.probe_min = c.probe;
-        int tm;
-        int64_t sl;
-        int64_t nmax = 1;
-        int32_t lcap = 3;
+    int64_t nmax = 1;
+    int32_t lcap = 3;
+    for (Query *q : qs) {
+        nmax = std::max<int64_t>(nmax, q->gd->n);
+        lcap = std::max(lcap, q->gd->vd + 2);
+    }
+    // slots_mul2 > 0: slots = the automatic count * slots_mul2 / 2; 0: t.slots as given
+    auto trial = [&](Params t, int64_t slots_mul2) -> int {
         for (Query *q : qs) {
-            nmax = std::max<int64_t>(nmax, q->gd->n);
-            lcap = std::max(lcap, q->gd->vd + 2);
-            q->probe_min = c.probe;
+            q->probe_min = t.probe_min;
+            q->epl = t.epochs;
+            q->nsets = 2 * t.epochs;
         }
-        t.slots = 0;
-        R.choose_mapping(t, nmax, lcap, &tm, &sl);
-        t.slots = std::max<int64_t>(1, sl * c.slots_mul2 / 2);
+        if (slots_mul2 > 0) {
+            int tm;
+            int64_t sl;
+            t.slots = 0;
+            R.choose_mapping(t, nmax, lcap, &tm, &sl);
+            t.slots = std::max<int64_t>(1, sl * slots_mul2 / 2);
+        }
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
             (size_t)t.slots * slot_bytes(nmax, lcap) > free_b / 2)
-            continue;
+            return KADABRA_OK;
         OK_OR_RETURN(run_queries(R, qs, t, trial_samples));  // warm-up: buffers, caches
         const auto t0 = std::chrono::steady_clock::now();
         OK_OR_RETURN(run_queries(R, qs, t, trial_samples));
@@ -1386,11 +1395,31 @@ int autotune(Runner &R, std::vector<Query *> &qs, Params &p, int64_t trial_sampl
             best = ms;
             best_p = t;
         }
+        return KADABRA_OK;
+    };
+    for (const Cand &c : cands) {
+        Params t = base;
+        t.team = c.team;
+        t.probe_min = c.probe;
+        OK_OR_RETURN(trial(t, c.slots_mul2));
+    }
+    // epochs per launch, on the best mapping so far (its slots are explicit)
+    const int first_epochs = best_p.epochs;
+    for (int e : {1, 2, 4}) {
+        if (e == first_epochs) continue;
+        Params t = best_p;
+        t.epochs = e;
+        OK_OR_RETURN(trial(t, 0));
     }
     p.team = best_p.team;
     p.slots = best_p.slots;
     p.probe_min = best_p.probe_min;
-    for (Query *q : qs) q->probe_min = p.probe_min;
+    p.epochs = best_p.epochs;
+    for (Query *q : qs) {
+        q->probe_min = p.probe_min;
+        q->epl = p.epochs;
+        q->nsets = 2 * p.epochs;
+    }
     return KADABRA_OK;
 }
 
@@ -2043,6 +2072,7 @@ int kadabra_run_static(kadabra_graph *g, double eps, double delta, uint64_t seed
         stats->e_bt = h.stats_total[kd::ST_EBT];
         stats->path_interior = h.stats_total[kd::ST_INTERIOR];
         stats->disconnected = h.stats_total[kd::ST_DISCONN];
+        stats->v_written = h.stats_total[kd::ST_VMAT];
         stats->log_inv_delta = L;
         stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         stats->sample_launches = epochs;

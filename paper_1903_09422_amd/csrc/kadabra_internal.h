@@ -12,14 +12,18 @@ struct Sigma {
     uint64_t lo, hi;
 };
 
-// Indices into the per-epoch work counters (int64).  Every counter is
-// algorithm-defined: it does not depend on the mapping of samples to lanes.
+// Indices into the per-epoch work counters (int64).  Every counter but
+// ST_VMAT is algorithm-defined: it does not depend on the mapping of samples
+// to lanes.
 enum StatIdx {
     ST_VEXP = 0,   // frontier vertices expanded
     ST_ESCAN,      // arcs scanned by expansions
     ST_EBT,        // arcs scanned while backtracking (sum of the path vertices' degrees)
     ST_INTERIOR,   // counter increments
     ST_DISCONN,    // samples with endpoints in different components
+    ST_VMAT,       // new vertices written (claimed) by level expansions: every new level in
+                   // full except a probed meeting level, which writes only the meeting set.
+                   // The one counter that depends on the mapping (the probe threshold).
     ST_COUNT
 };
 

@@ -932,6 +932,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
             PHASE_MARK(1);
             nN = uniform_i32(*cnt_new);
             nM = uniform_i32(*cnt_meet);
+            if (lane == 0) sm.acc[ST_VMAT] += (uint64_t)nN;
             // the next iteration counts in the other pair, last read before this
             // iteration's barriers
             if (lane == 0) {
