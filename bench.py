@@ -116,6 +116,8 @@ def main() -> int:
     ap.add_argument("--overlap", type=int, default=1)
     ap.add_argument("--epochs-per-launch", type=int, default=2)
     ap.add_argument("--probe-min", type=int, default=-1)
+    ap.add_argument("--probe-pull", type=int, default=0,
+                    help="1: meeting probes in the pull form (scan the other side's frontier rows)")
     ap.add_argument("--balanced-steps", type=int, default=10,
                     help="queries of the balanced leg (per-vertex delta_L, delta_U); 0: skip it")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -203,6 +205,7 @@ def measure_single(workload, args, steps, warmup, balanced_steps, with_cpu, copy
     dev.set_param("overlap", args.overlap)
     dev.set_param("epochs_per_launch", args.epochs_per_launch)
     dev.set_param("probe_min", args.probe_min)
+    dev.set_param("probe_pull", args.probe_pull)
     stream = torch.cuda.Stream()
     dev.set_stream(stream)
     scores = torch.empty(g.n, dtype=torch.float64, device="cuda")
@@ -271,7 +274,7 @@ def measure_single(workload, args, steps, warmup, balanced_steps, with_cpu, copy
             "mapping": {"team": dev.get_param("last_team"), "slots": dev.get_param("last_slots"),
                         "frames": args.frames, "overlap": args.overlap,
                         "epochs_per_launch": args.epochs_per_launch,
-                        "probe_min": args.probe_min},
+                        "probe_min": args.probe_min, "probe_pull": args.probe_pull},
         },
         "traversed_edges_per_s": escan / dt,
         "query_latency_ms": {"p50": float(np.percentile(lat, 50)),

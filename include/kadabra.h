@@ -136,6 +136,12 @@ int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr,
  *                     for the meeting set without materialising the new level;
  *                     -1 (default): when the product of the two frontiers'
  *                     degree sums reaches four times the arc count.
+ *   "probe_pull"      1: a meeting probe scans the rows of the other side's
+ *                     frontier for neighbours on the expanding side's
+ *                     frontier (pull form) instead of the expanding side's
+ *                     rows (push form); the same meeting set and path counts
+ *                     either way.  256-lane teams only (others push).
+ *                     Default 0.
  *   "test_fail_alloc" k >= 1: the k-th device allocation of the next run's
  *                     buffers fails with ENOMEM (failure-path testing); 0: off.
  *   "test_level_cap"  k >= 3: the sampler is given room for only k BFS levels

@@ -199,6 +199,7 @@ struct Params {
     int overlap = 1;
     int epochs = 2;          // epochs (check intervals) per sampling launch, 1..4
     int64_t probe_min = -1;  // -1 auto rule
+    int probe_pull = 0;      // 1: meeting probes in the pull form (256-lane teams)
     int balance = 0;         // 1: per-vertex delta_L, delta_U from a first sampling phase
     int64_t balance_samples = 0;  // first-phase samples; 0: ceil(omega / 20)
     int64_t fail_alloc = 0;  // test hook
@@ -231,6 +232,9 @@ int set_common_param(Params &p, const char *key, int64_t value, bool *known)
     } else if (!strcmp(key, "probe_min")) {
         if (value < -1) return fail(KADABRA_EINVAL, "probe_min must be >= -1");
         p.probe_min = value;
+    } else if (!strcmp(key, "probe_pull")) {
+        if (value != 0 && value != 1) return fail(KADABRA_EINVAL, "probe_pull must be 0 or 1");
+        p.probe_pull = (int)value;
     } else if (!strcmp(key, "balance")) {
         if (value != 0 && value != 1) return fail(KADABRA_EINVAL, "balance must be 0 or 1");
         p.balance = (int)value;
@@ -260,6 +264,7 @@ int get_common_param(const Params &p, const char *key, int64_t *value)
     else if (!strcmp(key, "overlap")) *value = p.overlap;
     else if (!strcmp(key, "epochs_per_launch")) *value = p.epochs;
     else if (!strcmp(key, "probe_min")) *value = p.probe_min;
+    else if (!strcmp(key, "probe_pull")) *value = p.probe_pull;
     else if (!strcmp(key, "balance")) *value = p.balance;
     else if (!strcmp(key, "balance_samples")) *value = p.balance_samples;
     else if (!strcmp(key, "test_level_cap")) *value = p.level_cap;
@@ -929,7 +934,7 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
         HIP_OR_FAIL(hipEventRecord(L.e0, stream));
         bool mapped = false;
         for (Query *q : qs) mapped = mapped || q->gd->d_perm != nullptr;
-        HIP_OR_FAIL(kd::launch_sample(team, grid, sa, mapped, stream));
+        HIP_OR_FAIL(kd::launch_sample(team, grid, sa, mapped, p.probe_pull != 0, stream));
         HIP_OR_FAIL(hipEventRecord(L.e1, stream));
         pend.push_back(std::move(L));
         // the balanced constants, from the finished first phase, before any
@@ -2027,7 +2032,7 @@ int kadabra_run_static(kadabra_graph *g, double eps, double delta, uint64_t seed
         sa.st = st;
         const int grid = (int)std::min<int64_t>(slots, hi - lo);
         claim_next += (uint64_t)(hi - lo) + (uint64_t)grid;
-        HIP_OR_FAIL(kd::launch_sample(team, grid, sa, gd.d_perm != nullptr, s));
+        HIP_OR_FAIL(kd::launch_sample(team, grid, sa, gd.d_perm != nullptr, p.probe_pull != 0, s));
         kd::MergeArgs ma{};
         ma.m = nullptr;
         ma.nq = 1;

@@ -137,8 +137,9 @@ struct MergeArgs {
 // counter above m1 cannot occur and is reported as device error 4).  The
 // host then plans t* and the constant table lcon from the histogram.
 
-// mapped: some query of the launch is on a relabelled graph
-hipError_t launch_sample(int team, int slots, const SampleArgs &a, bool mapped, hipStream_t s);
+// mapped: some query of the launch is on a relabelled graph; pull: meeting
+// probes in the pull form (256-lane teams; other teams push)
+hipError_t launch_sample(int team, int slots, const SampleArgs &a, bool mapped, bool pull, hipStream_t s);
 hipError_t launch_hist(const int32_t *c1, int32_t n, int32_t *hist, int64_t m1, Control *ctl, hipStream_t s);
 hipError_t launch_merge_check(const MergeArgs &a, hipStream_t s);
 int32_t merge_blocks_for(int32_t n);

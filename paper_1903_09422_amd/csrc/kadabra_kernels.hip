@@ -518,8 +518,9 @@ __device__ __forceinline__ void clear_ball(const int32_t *ball, int32_t len, uin
 // Wave/workgroup-per-sample sampler.  Every lane of the team runs the same
 // control flow; per-sample scalars live in registers (uniform) or LDS.
 // MAPPED: some query of the launch is on a relabelled graph (its descriptor
-// has the vertex maps); without it the maps are never read.
-template <int TEAM, bool MAPPED>
+// has the vertex maps); without it the maps are never read.  PULL: meeting
+// probes take the pull form (scan the other side's frontier rows).
+template <int TEAM, bool MAPPED, bool PULL>
 __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void sample_kernel(SampleArgs a)
 {
     using T = Team<TEAM>;
@@ -772,162 +773,270 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
             int32_t *const hkeys = reinterpret_cast<int32_t *>(&sm.fsg[X][0]);  // 4 TEAM >= STAGE ints
             constexpr int32_t HMASK = STAGE - 1;
             constexpr int32_t HMAX = STAGE / 2;  // at most half of the slots are filled
-            for (int32_t c0 = flox; c0 < fhix; c0 += TEAM) {
-                const int32_t idx = c0 + lane;
-                int32_t dg = 0;
-                if (idx < fhix) {
-                    if (fcx) {
-                        dg = sm.fdg[X][lane];
-                        sm.crs[lane] = sm.frs[X][lane];
-                        sm.cm[lane] = sm.fsg[X][lane];
-                    } else {
-                        const int32_t u = ballx[idx];
-                        const int32_t rs = row_ptr[u];
-                        dg = row_ptr[u + 1] - rs;
-                        sm.crs[lane] = rs;
-                        sm.cm[lane] = sigx[u];
-                    }
-                }
-                if (lds_try) {
-                    // each lane empties the key slots of its own cache entry (read above)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) hkeys[4 * lane + j] = -1;
-                    for (int32_t h = lane; h < STAGE; h += TEAM) sm.sw[h] = Sigma{0u, 0u};
-                }
-                int32_t tot;
-                const int32_t ex = T::excl_scan_i32(dg, &tot, redA);
-                sm.cpfx[lane] = ex;
-                const int32_t cnt = min(TEAM, fhix - c0);
-                __syncthreads();
-                // Each lane takes arcs lane, lane + TEAM, ... ARCS at a time: all
-                // their owners, column entries and code words are fetched before
-                // any is processed.  A lane's owners only move forward, so each
-                // is found by galloping from the previous one.
-                int32_t own = 0;
-                auto owner_of = [&](int32_t e) {
-                    int32_t step = 1;
-                    while (own + step < cnt && sm.cpfx[own + step] <= e) {
-                        own += step;
-                        step <<= 1;
-                    }
-                    int32_t hi = min(own + step, cnt);
-                    while (hi - own > 1) {
-                        const int32_t mid = (own + hi) >> 1;
-                        if (sm.cpfx[mid] <= e) own = mid; else hi = mid;
-                    }
-                    return own;
-                };
-                // One round: arcs e, e + TEAM, ... (up to ARCS) of this lane --
-                // owners, column entries, code words, claims and appends.  wv,
-                // ow and add receive the arcs and which of them enter the new level.
-                auto claim_round = [&](int32_t e, int32_t (&wv)[ARCS], int32_t (&ow)[ARCS], bool (&add)[ARCS]) {
-                    // owners and arc positions (LDS only); an arc past the end
-                    // repeats arc e so that every load below is unconditional
-                    int32_t ai[ARCS];
-                    uint32_t wd[ARCS];
-#pragma unroll
-                    for (int k = 0; k < ARCS; ++k) {
-                        const int32_t ek = e + k * TEAM;
-                        if (k == 0 || ek < tot) {
-                            ow[k] = owner_of(ek);
-                            ai[k] = sm.crs[ow[k]] + (ek - sm.cpfx[ow[k]]);
+            if (PULL && probe) {
+                // Pull form of the meeting probe: the rows of Y's frontier are
+                // scanned for neighbours on X's frontier.  Such a neighbour p
+                // makes the row's vertex y a meeting vertex, and sigma_X(y) is
+                // the sum of sigma_X(p) over them: the same set and the same sums
+                // as the push form, because no vertex is reached by both sides
+                // before the level on which they meet and every meeting vertex
+                // lies on Y's frontier.  (A neighbour with X's frontier code mod 3
+                // lies on X's frontier itself: one three levels closer to X's root
+                // would have made y reached by X already.)
+                constexpr int PA = ARCS / 2;  // arcs in flight per lane
+                const int Y = X ^ 1;
+                const int32_t *const bally = Y ? ball1 : ball0;
+                const int32_t floy = Y ? flo1 : flo0, fhiy = Y ? fhi1 : fhi0;
+                const bool fcy = Y ? fc1 : fc0;
+                const uint32_t code_front = level_code(lvlx);
+                for (int32_t c0 = floy; c0 < fhiy; c0 += TEAM) {
+                    const int32_t idx = c0 + lane;
+                    int32_t dg = 0;
+                    if (idx < fhiy) {
+                        const int32_t y = bally[idx];
+                        if (fcy) {
+                            dg = sm.fdg[Y][lane];
+                            sm.crs[lane] = sm.frs[Y][lane];
                         } else {
-                            ow[k] = ow[0];
-                            ai[k] = ai[0];
+                            const int32_t rs = row_ptr[y];
+                            dg = row_ptr[y + 1] - rs;
+                            sm.crs[lane] = rs;
+                        }
+                        sm.cm[lane].lo = (uint64_t)(uint32_t)y;  // the row's vertex
+                    }
+                    int32_t tot;
+                    const int32_t ex = T::excl_scan_i32(dg, &tot, redA);
+                    sm.cpfx[lane] = ex;
+                    const int32_t cnt = min(TEAM, fhiy - c0);
+                    __syncthreads();
+                    int32_t own = 0;
+                    auto owner_of = [&](int32_t e) {
+                        int32_t step = 1;
+                        while (own + step < cnt && sm.cpfx[own + step] <= e) {
+                            own += step;
+                            step <<= 1;
+                        }
+                        int32_t hi = min(own + step, cnt);
+                        while (hi - own > 1) {
+                            const int32_t mid = (own + hi) >> 1;
+                            if (sm.cpfx[mid] <= e) own = mid; else hi = mid;
+                        }
+                        return own;
+                    };
+                    for (int32_t e = lane; e < tot; e += PA * TEAM) {
+                        int32_t ai[PA], yv[PA], pv[PA];
+                        uint32_t wd[PA], old[PA];
+                        bool hit[PA];
+                        Sigma sp[PA];
+#pragma unroll
+                        for (int k = 0; k < PA; ++k) {
+                            const int32_t ek = e + k * TEAM;
+                            int32_t o = own;
+                            if (k == 0 || ek < tot) {
+                                o = owner_of(ek);
+                                ai[k] = sm.crs[o] + (ek - sm.cpfx[o]);
+                            } else {
+                                ai[k] = ai[0];
+                            }
+                            yv[k] = (int32_t)(uint32_t)sm.cm[o].lo;
+                        }
+#pragma unroll
+                        for (int k = 0; k < PA; ++k) pv[k] = col[ai[k]];
+#pragma unroll
+                        for (int k = 0; k < PA; ++k) wd[k] = code[pv[k] >> 3];
+#pragma unroll
+                        for (int k = 0; k < PA; ++k) {
+                            hit[k] = (k == 0 || e + k * TEAM < tot) &&
+                                     ((wd[k] >> code_shift(pv[k], X)) & 3u) == code_front;
+                            sp[k] = hit[k] ? sigx[pv[k]] : Sigma{0u, 0u};
+                        }
+#pragma unroll
+                        for (int k = 0; k < PA; ++k)
+                            old[k] = hit[k] ? wg_or_u32(&code[yv[k] >> 3], code_new << code_shift(yv[k], X)) : 0u;
+#pragma unroll
+                        for (int k = 0; k < PA; ++k) {
+                            const bool claimed = hit[k] && ((old[k] >> code_shift(yv[k], X)) & 3u) == 0u;
+                            const int pp = wave_append(claimed, cnt_new);
+                            if (claimed) {
+                                ballx[base_new + pp] = yv[k];
+                                if (pp < STAGE) sm.sv[pp] = yv[k];
+                            }
+                            const int q = wave_append(claimed, cnt_meet);
+                            if (claimed) meet[q] = yv[k];
+                        }
+                        // sigma_X(y) += sigma_X(p)
+#pragma unroll
+                        for (int k = 0; k < PA; ++k) {
+                            if (!hit[k]) continue;
+                            if (low_mass) {
+                                (void)wg_add_u64(&sigx[yv[k]].lo, sp[k].lo);
+                            } else {
+                                const uint64_t o = wg_add_u64(&sigx[yv[k]].lo, sp[k].lo);
+                                const uint64_t hi = sp[k].hi + ((o + sp[k].lo) < o ? 1u : 0u);
+                                if (hi) wg_add_u64(&sigx[yv[k]].hi, hi);
+                            }
                         }
                     }
-#pragma unroll
-                    for (int k = 0; k < ARCS; ++k) wv[k] = col[ai[k]];
-#pragma unroll
-                    for (int k = 0; k < ARCS; ++k) wd[k] = code[wv[k] >> 3];
-                    // claims: decided from the words read, and all issued before
-                    // any result is awaited.  Every claim on this level writes the
-                    // same code, so an OR into a field another lane (or an earlier
-                    // arc of this lane) just set changes nothing.
-                    uint32_t dxc[ARCS], dyc[ARCS], old[ARCS];
-                    bool cand[ARCS];
-#pragma unroll
-                    for (int k = 0; k < ARCS; ++k) {
-                        const bool valid = k == 0 || e + k * TEAM < tot;
-                        dxc[k] = (wd[k] >> code_shift(wv[k], X)) & 3u;
-                        dyc[k] = (wd[k] >> code_shift(wv[k], X ^ 1)) & 3u;
-                        cand[k] = valid && dxc[k] == 0u && (!probe || dyc[k] != 0u);
-                    }
-#pragma unroll
-                    for (int k = 0; k < ARCS; ++k)
-                        old[k] = cand[k] ? wg_or_u32(&code[wv[k] >> 3], code_new << code_shift(wv[k], X)) : 0u;
-#pragma unroll
-                    for (int k = 0; k < ARCS; ++k) {
-                        const int32_t w = wv[k];
-                        bool claimed = false;
-                        if (cand[k]) {
-                            const uint32_t o = (old[k] >> code_shift(w, X)) & 3u;
-                            claimed = (o == 0u);
-                            dxc[k] = claimed ? code_new : o;
-                        }
-                        const int p = wave_append(claimed, cnt_new);
-                        if (claimed) {
-                            ballx[base_new + p] = w;
-                            if (p < STAGE) sm.sv[p] = w;
-                            if (lds_try && p < HMAX) hash_insert(hkeys, HMASK, w);
-                        }
-                        const bool is_meet = claimed && dyc[k] != 0u;
-                        const int q = wave_append(is_meet, cnt_meet);
-                        if (is_meet) meet[q] = w;
-                        add[k] = (k == 0 || e + k * TEAM < tot) && dxc[k] == code_new;
-                    }
-                };
-                // sigma(w) += sigma(owner) for every arc into the new level, in
-                // global memory: all low-word adds first, then the carries.  When
-                // the frontier's mass is below 2^63 no count of the new level can
-                // leave the low word, so the adds need no result and no wait.
-                auto global_adds = [&](const int32_t (&wv)[ARCS], const int32_t (&ow)[ARCS],
-                                       const bool (&add)[ARCS]) {
-                    if (low_mass) {
-#pragma unroll
-                        for (int k = 0; k < ARCS; ++k)
-                            if (add[k]) (void)wg_add_u64(&sigx[wv[k]].lo, sm.cm[ow[k]].lo);
-                        return;
-                    }
-                    uint64_t olo[ARCS];
-#pragma unroll
-                    for (int k = 0; k < ARCS; ++k) olo[k] = 0u;
-#pragma unroll
-                    for (int k = 0; k < ARCS; ++k)
-                        if (add[k]) olo[k] = wg_add_u64(&sigx[wv[k]].lo, sm.cm[ow[k]].lo);
-#pragma unroll
-                    for (int k = 0; k < ARCS; ++k) {
-                        if (!add[k]) continue;
-                        const Sigma m = sm.cm[ow[k]];
-                        const uint64_t hi = m.hi + ((olo[k] + m.lo) < olo[k] ? 1u : 0u);
-                        if (hi) wg_add_u64(&sigx[wv[k]].hi, hi);
-                    }
-                };
-                int32_t wv[ARCS], ow[ARCS];
-                bool add[ARCS];
-#pragma unroll
-                for (int k = 0; k < ARCS; ++k) add[k] = false;
-                for (int32_t e = lane; e < tot; e += ARCS * TEAM) {
-                    claim_round(e, wv, ow, add);
-                    if (!lds_try) global_adds(wv, ow, add);  // else: one round, added below
+                    __syncthreads();
                 }
-                if (lds_try) {
-                    __syncthreads();  // the claims are done and the set is filled
-                    if (uniform_i32(*cnt_new) <= HMAX) {
-#pragma unroll
+            } else {
+                for (int32_t c0 = flox; c0 < fhix; c0 += TEAM) {
+                    const int32_t idx = c0 + lane;
+                    int32_t dg = 0;
+                    if (idx < fhix) {
+                        if (fcx) {
+                            dg = sm.fdg[X][lane];
+                            sm.crs[lane] = sm.frs[X][lane];
+                            sm.cm[lane] = sm.fsg[X][lane];
+                        } else {
+                            const int32_t u = ballx[idx];
+                            const int32_t rs = row_ptr[u];
+                            dg = row_ptr[u + 1] - rs;
+                            sm.crs[lane] = rs;
+                            sm.cm[lane] = sigx[u];
+                        }
+                    }
+                    if (lds_try) {
+                        // each lane empties the key slots of its own cache entry (read above)
+    #pragma unroll
+                        for (int j = 0; j < 4; ++j) hkeys[4 * lane + j] = -1;
+                        for (int32_t h = lane; h < STAGE; h += TEAM) sm.sw[h] = Sigma{0u, 0u};
+                    }
+                    int32_t tot;
+                    const int32_t ex = T::excl_scan_i32(dg, &tot, redA);
+                    sm.cpfx[lane] = ex;
+                    const int32_t cnt = min(TEAM, fhix - c0);
+                    __syncthreads();
+                    // Each lane takes arcs lane, lane + TEAM, ... ARCS at a time: all
+                    // their owners, column entries and code words are fetched before
+                    // any is processed.  A lane's owners only move forward, so each
+                    // is found by galloping from the previous one.
+                    int32_t own = 0;
+                    auto owner_of = [&](int32_t e) {
+                        int32_t step = 1;
+                        while (own + step < cnt && sm.cpfx[own + step] <= e) {
+                            own += step;
+                            step <<= 1;
+                        }
+                        int32_t hi = min(own + step, cnt);
+                        while (hi - own > 1) {
+                            const int32_t mid = (own + hi) >> 1;
+                            if (sm.cpfx[mid] <= e) own = mid; else hi = mid;
+                        }
+                        return own;
+                    };
+                    // One round: arcs e, e + TEAM, ... (up to ARCS) of this lane --
+                    // owners, column entries, code words, claims and appends.  wv,
+                    // ow and add receive the arcs and which of them enter the new level.
+                    auto claim_round = [&](int32_t e, int32_t (&wv)[ARCS], int32_t (&ow)[ARCS], bool (&add)[ARCS]) {
+                        // owners and arc positions (LDS only); an arc past the end
+                        // repeats arc e so that every load below is unconditional
+                        int32_t ai[ARCS];
+                        uint32_t wd[ARCS];
+    #pragma unroll
+                        for (int k = 0; k < ARCS; ++k) {
+                            const int32_t ek = e + k * TEAM;
+                            if (k == 0 || ek < tot) {
+                                ow[k] = owner_of(ek);
+                                ai[k] = sm.crs[ow[k]] + (ek - sm.cpfx[ow[k]]);
+                            } else {
+                                ow[k] = ow[0];
+                                ai[k] = ai[0];
+                            }
+                        }
+    #pragma unroll
+                        for (int k = 0; k < ARCS; ++k) wv[k] = col[ai[k]];
+    #pragma unroll
+                        for (int k = 0; k < ARCS; ++k) wd[k] = code[wv[k] >> 3];
+                        // claims: decided from the words read, and all issued before
+                        // any result is awaited.  Every claim on this level writes the
+                        // same code, so an OR into a field another lane (or an earlier
+                        // arc of this lane) just set changes nothing.
+                        uint32_t dxc[ARCS], dyc[ARCS], old[ARCS];
+                        bool cand[ARCS];
+    #pragma unroll
+                        for (int k = 0; k < ARCS; ++k) {
+                            const bool valid = k == 0 || e + k * TEAM < tot;
+                            dxc[k] = (wd[k] >> code_shift(wv[k], X)) & 3u;
+                            dyc[k] = (wd[k] >> code_shift(wv[k], X ^ 1)) & 3u;
+                            cand[k] = valid && dxc[k] == 0u && (!probe || dyc[k] != 0u);
+                        }
+    #pragma unroll
+                        for (int k = 0; k < ARCS; ++k)
+                            old[k] = cand[k] ? wg_or_u32(&code[wv[k] >> 3], code_new << code_shift(wv[k], X)) : 0u;
+    #pragma unroll
+                        for (int k = 0; k < ARCS; ++k) {
+                            const int32_t w = wv[k];
+                            bool claimed = false;
+                            if (cand[k]) {
+                                const uint32_t o = (old[k] >> code_shift(w, X)) & 3u;
+                                claimed = (o == 0u);
+                                dxc[k] = claimed ? code_new : o;
+                            }
+                            const int p = wave_append(claimed, cnt_new);
+                            if (claimed) {
+                                ballx[base_new + p] = w;
+                                if (p < STAGE) sm.sv[p] = w;
+                                if (lds_try && p < HMAX) hash_insert(hkeys, HMASK, w);
+                            }
+                            const bool is_meet = claimed && dyc[k] != 0u;
+                            const int q = wave_append(is_meet, cnt_meet);
+                            if (is_meet) meet[q] = w;
+                            add[k] = (k == 0 || e + k * TEAM < tot) && dxc[k] == code_new;
+                        }
+                    };
+                    // sigma(w) += sigma(owner) for every arc into the new level, in
+                    // global memory: all low-word adds first, then the carries.  When
+                    // the frontier's mass is below 2^63 no count of the new level can
+                    // leave the low word, so the adds need no result and no wait.
+                    auto global_adds = [&](const int32_t (&wv)[ARCS], const int32_t (&ow)[ARCS],
+                                           const bool (&add)[ARCS]) {
+                        if (low_mass) {
+    #pragma unroll
+                            for (int k = 0; k < ARCS; ++k)
+                                if (add[k]) (void)wg_add_u64(&sigx[wv[k]].lo, sm.cm[ow[k]].lo);
+                            return;
+                        }
+                        uint64_t olo[ARCS];
+    #pragma unroll
+                        for (int k = 0; k < ARCS; ++k) olo[k] = 0u;
+    #pragma unroll
+                        for (int k = 0; k < ARCS; ++k)
+                            if (add[k]) olo[k] = wg_add_u64(&sigx[wv[k]].lo, sm.cm[ow[k]].lo);
+    #pragma unroll
                         for (int k = 0; k < ARCS; ++k) {
                             if (!add[k]) continue;
-                            Sigma *const q = &sm.sw[hash_find(hkeys, HMASK, wv[k])];
-                            if (low_mass)  // no carry possible: an add without a result
-                                (void)atomicAdd((unsigned long long *)&q->lo, (unsigned long long)sm.cm[ow[k]].lo);
-                            else
-                                lds_add128(q, sm.cm[ow[k]]);
+                            const Sigma m = sm.cm[ow[k]];
+                            const uint64_t hi = m.hi + ((olo[k] + m.lo) < olo[k] ? 1u : 0u);
+                            if (hi) wg_add_u64(&sigx[wv[k]].hi, hi);
                         }
-                    } else {
-                        global_adds(wv, ow, add);
+                    };
+                    int32_t wv[ARCS], ow[ARCS];
+                    bool add[ARCS];
+    #pragma unroll
+                    for (int k = 0; k < ARCS; ++k) add[k] = false;
+                    for (int32_t e = lane; e < tot; e += ARCS * TEAM) {
+                        claim_round(e, wv, ow, add);
+                        if (!lds_try) global_adds(wv, ow, add);  // else: one round, added below
                     }
+                    if (lds_try) {
+                        __syncthreads();  // the claims are done and the set is filled
+                        if (uniform_i32(*cnt_new) <= HMAX) {
+    #pragma unroll
+                            for (int k = 0; k < ARCS; ++k) {
+                                if (!add[k]) continue;
+                                Sigma *const q = &sm.sw[hash_find(hkeys, HMASK, wv[k])];
+                                if (low_mass)  // no carry possible: an add without a result
+                                    (void)atomicAdd((unsigned long long *)&q->lo, (unsigned long long)sm.cm[ow[k]].lo);
+                                else
+                                    lds_add128(q, sm.cm[ow[k]]);
+                            }
+                        } else {
+                            global_adds(wv, ow, add);
+                        }
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
             }
             PHASE_MARK(1);
             nN = uniform_i32(*cnt_new);
@@ -1423,27 +1532,29 @@ static unsigned grid_for(size_t count, unsigned block)
 }
 
 template <bool MAPPED>
-static hipError_t launch_sample_as(int team, int slots, const SampleArgs &a, hipStream_t s)
+static hipError_t launch_sample_as(int team, int slots, const SampleArgs &a, bool pull, hipStream_t s)
 {
 #ifndef KADABRA_PHASE_TIMERS
     if (team == 64)
-        hipLaunchKernelGGL((sample_kernel<64, MAPPED>), dim3(slots), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((sample_kernel<64, MAPPED, false>), dim3(slots), dim3(64), 0, s, a);
     else
 #endif
     if (team == 128)
-        hipLaunchKernelGGL((sample_kernel<128, MAPPED>), dim3(slots), dim3(128), 0, s, a);
+        hipLaunchKernelGGL((sample_kernel<128, MAPPED, false>), dim3(slots), dim3(128), 0, s, a);
+    else if (team == 256 && pull)
+        hipLaunchKernelGGL((sample_kernel<256, MAPPED, true>), dim3(slots), dim3(256), 0, s, a);
     else if (team == 256)
-        hipLaunchKernelGGL((sample_kernel<256, MAPPED>), dim3(slots), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((sample_kernel<256, MAPPED, false>), dim3(slots), dim3(256), 0, s, a);
     else if (team == 512)
-        hipLaunchKernelGGL((sample_kernel<512, MAPPED>), dim3(slots), dim3(512), 0, s, a);
+        hipLaunchKernelGGL((sample_kernel<512, MAPPED, false>), dim3(slots), dim3(512), 0, s, a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-hipError_t launch_sample(int team, int slots, const SampleArgs &a, bool mapped, hipStream_t s)
+hipError_t launch_sample(int team, int slots, const SampleArgs &a, bool mapped, bool pull, hipStream_t s)
 {
-    return mapped ? launch_sample_as<true>(team, slots, a, s) : launch_sample_as<false>(team, slots, a, s);
+    return mapped ? launch_sample_as<true>(team, slots, a, pull, s) : launch_sample_as<false>(team, slots, a, pull, s);
 }
 
 hipError_t launch_merge_check(const MergeArgs &a, hipStream_t s)

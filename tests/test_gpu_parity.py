@@ -64,6 +64,17 @@ def test_small_graphs(g, team, probe):
         assert_same(got, want)
 
 
+@pytest.mark.parametrize("probe", [-1, 0])
+@pytest.mark.parametrize("g", SMALL, ids=lambda g: g.name)
+def test_small_graphs_pull_probe(g, probe):
+    """The pull form of the meeting probe gives the oracle's result."""
+    print(f"case {g.name} pull probe, probe_min={probe}", flush=True)
+    for seed, n_check in ((1, 64), (9, 333)):
+        want = oracle.run(g, 0.05, 0.1, seed, n_check)
+        got = gpu_run(g, 0.05, 0.1, seed, n_check, team=256, probe_min=probe, probe_pull=1)
+        assert_same(got, want)
+
+
 @pytest.mark.parametrize("n_check", [1, 7, 1000, 10**6])
 def test_check_intervals_and_ragged_last_epoch(n_check):
     """Every check interval, with one to four epochs per sampling launch (a run
@@ -142,8 +153,8 @@ def test_layered_graph_with_huge_sigma():
     g = G.from_edges(layers * width, u, v, lcc=False)
     print("case layered 80x17", flush=True)
     want = oracle.run(g, 0.05, 0.1, 2, 512)
-    for team, probe in ((64, -1), (256, -1), (256, 0)):
-        got = gpu_run(g, 0.05, 0.1, 2, 512, team=team, probe_min=probe)
+    for team, probe, pull in ((64, -1, 0), (256, -1, 0), (256, 0, 0), (256, 0, 1)):
+        got = gpu_run(g, 0.05, 0.1, 2, 512, team=team, probe_min=probe, probe_pull=pull)
         assert_same(got, want)
 
 
@@ -202,7 +213,8 @@ def test_mapping_does_not_change_results():
                    {"team": 128, "slots": 2048}, {"epochs_per_launch": 1}, {"epochs_per_launch": 3},
                    {"epochs_per_launch": 4, "overlap": 0},
                    {"frames": 8}, {"overlap": 0}, {"team": 64, "frames": 3, "overlap": 0},
-                   {"probe_min": 0}, {"probe_min": 1 << 40}, {"team": 64, "probe_min": 0}):
+                   {"probe_min": 0}, {"probe_min": 1 << 40}, {"team": 64, "probe_min": 0},
+                   {"probe_pull": 1}, {"probe_pull": 1, "probe_min": 0}):
         print("  mapping", params, flush=True)
         got = gpu_run(g, eps, delta, ref["seed"], n_check, **params)
         assert got.tau == base.tau and np.array_equal(got.counts, base.counts), params
