@@ -99,6 +99,37 @@ def cpu_baseline(g, eps, delta, seed, n_check, min_seconds, max_repeats):
                       f"(tau={r.tau} each), single-threaded, {dt:.1f} s"}
 
 
+def host_threads() -> int:
+    """Host threads this process may use (its CPU affinity), at most 16 (the
+    host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline_threads(g, eps, delta, seed, n_check, min_seconds, max_repeats):
+    """The oracle's adaptive loop on all usable host threads (per-thread
+    counter frames of each epoch's samples, added at every boundary; the
+    result equals the single-threaded oracle's), repeated as cpu_baseline."""
+    import oracle
+
+    threads = host_threads()
+    t0 = time.perf_counter()
+    samples = repeats = 0
+    while True:
+        r = oracle.run_threads(g, eps, delta, seed, n_check, threads)
+        samples += r.tau
+        repeats += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds or repeats >= max_repeats:
+            break
+    return {"value": samples / dt, "unit": "samples/s", "cores": threads, "kind": "oracle-threads",
+            "sample": f"{repeats} complete threaded oracle run(s) of the same workload and seed "
+                      f"(tau={r.tau} each), {threads} threads, {dt:.1f} s"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,6 +335,8 @@ def measure_single(workload, args, steps, warmup, balanced_steps, with_cpu, copy
     if with_cpu:
         out["cpu_baseline"] = cpu_baseline(g, eps, delta, args.seed, n_check, args.cpu_seconds,
                                            args.cpu_repeats)
+        out["cpu_baseline_threads"] = cpu_baseline_threads(g, eps, delta, args.seed, n_check,
+                                                           args.cpu_seconds / 2, args.cpu_repeats)
     dev.close()
     return out
 

@@ -17,7 +17,7 @@ _SRC = os.path.join(_HERE, "kadabra_oracle.c")
 # ORACLE_LIB names another build of the oracle (for example one with
 # sanitizers); by default the in-tree build is loaded.
 _LIB = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
-CFLAGS = ["-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off", "-fPIC", "-shared"]
+CFLAGS = ["-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off", "-fPIC", "-shared", "-pthread"]
 
 
 SAN_LIB = os.path.join(os.path.dirname(_HERE), "_build", "liboracle_san.so")
@@ -101,6 +101,9 @@ def lib():
         L.oracle_setup.argtypes = [C.c_int32, i32p, i32p, C.c_double, C.c_double, i32p,
                                    C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_double)]
+        L.oracle_run_threads.argtypes = [C.c_int32, i32p, i32p, C.c_double, C.c_double, C.c_uint64,
+                                         C.c_int64, C.c_int32, i32p, C.POINTER(Stats),
+                                         np.ctypeslib.ndpointer(np.int8, flags="C_CONTIGUOUS"), C.c_int64]
         L.oracle_run.argtypes = [C.c_int32, i32p, i32p, C.c_double, C.c_double, C.c_uint64,
                                  C.c_int64, C.c_int64, i32p, C.POINTER(Stats),
                                  np.ctypeslib.ndpointer(np.int8, flags="C_CONTIGUOUS"), C.c_int64]
@@ -283,6 +286,21 @@ def run(g, eps: float, delta: float, seed: int, check_interval: int,
     if first_samples != 0:
         r.LL, r.LU, r.c1 = LL, LU, c1
     return r
+
+
+def run_threads(g, eps: float, delta: float, seed: int, check_interval: int, threads: int) -> RunResult:
+    """The adaptive loop on `threads` host threads (per-thread counter frames
+    of each epoch's samples, split by index, added at every boundary)."""
+    n, rp, col = _csr(g)
+    counts = np.zeros(n, dtype=np.int32)
+    st = Stats()
+    dec = np.full(1 << 16, -1, dtype=np.int8)
+    rc = lib().oracle_run_threads(n, rp, col, eps, delta, seed, check_interval, threads, counts,
+                                  C.byref(st), dec, dec.size)
+    if rc != 0:
+        raise ValueError(f"oracle_run_threads failed ({rc})")
+    ne = min(int(st.epochs), dec.size)
+    return RunResult(tau=int(st.tau), counts=counts, stats=st.as_dict(), decisions=dec[:ne].copy())
 
 
 def sample(g, comp, seed: int, i: int):

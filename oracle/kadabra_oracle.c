@@ -35,6 +35,7 @@
  * stop test must evaluate the exact IEEE expression tree given below).
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -832,6 +833,117 @@ int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, double eps
 {
     return oracle_run_balanced(n, row_ptr, col, eps, delta, seed, check_interval, sample_cap, 0,
                                counts, st, decisions, max_decisions, NULL, NULL, NULL);
+}
+
+/* ------------------------------------------------------------------------ */
+/* The same adaptive loop on T threads (the CPU baseline on all host cores):  */
+/* the local-frame idea of Section 3 with the indexed-frame assignment of    */
+/* Appendix D.2.  In each epoch [B_{k-1}, B_k), thread t draws the samples    */
+/* i = B_{k-1} + t, + T, ... into its own counter frame; the frames are added */
+/* into the counters at the boundary, and only then is the stopping rule      */
+/* checked, on exactly the samples [0, B_k).  Sample i depends on i alone and */
+/* the sums are integer, so tau and every counter equal oracle_run's.         */
+/* ------------------------------------------------------------------------ */
+
+struct thread_part {
+    struct sampler S;
+    int32_t *frame, *interior;
+    oracle_stats st;
+    uint64_t seed;
+    int64_t lo, hi, stride;
+};
+
+static void *thread_epoch(void *arg)
+{
+    struct thread_part *P = (struct thread_part *)arg;
+    for (int64_t i = P->lo; i < P->hi; i += P->stride) {
+        int32_t ni = sample_path(&P->S, P->seed, (uint64_t)i, P->interior, NULL, &P->st, -1, -1);
+        if (ni < 0) { P->st.disconnected += 1; continue; }
+        for (int32_t q = 0; q < ni; ++q) P->frame[P->interior[q]] += 1;
+    }
+    return NULL;
+}
+
+int oracle_run_threads(int32_t n, const int32_t *row_ptr, const int32_t *col, double eps, double delta,
+                       uint64_t seed, int64_t check_interval, int32_t threads, int32_t *counts,
+                       oracle_stats *st, int8_t *decisions, int64_t max_decisions)
+{
+    if (check_interval < 1 || threads < 1 || threads > 1024) return -1;
+    memset(st, 0, sizeof(*st));
+    int32_t *comp = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    struct thread_part *P = (struct thread_part *)calloc((size_t)threads, sizeof *P);
+    pthread_t *tid = (pthread_t *)calloc((size_t)threads, sizeof *tid);
+    int rc = -2;
+    int32_t made = 0;
+    if (!comp || !P || !tid) goto out;
+    int32_t vd;
+    int64_t omega;
+    double L;
+    if (oracle_setup(n, row_ptr, col, eps, delta, comp, &vd, &omega, &L) != 0) { rc = -1; goto out; }
+    st->vd = vd; st->omega = omega; st->L = L;
+    for (; made < threads; ++made) {
+        struct thread_part *p = &P[made];
+        p->frame = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+        p->interior = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        if (!p->frame || !p->interior || sampler_init(&p->S, n, row_ptr, col, comp) != 0) {
+            free(p->frame); free(p->interior);
+            goto out;
+        }
+        p->seed = seed;
+        p->stride = threads;
+    }
+    for (int32_t v = 0; v < n; ++v) counts[v] = 0;
+    int64_t tau = 0, k = 0;
+    for (;;) {
+        ++k;
+        int64_t hi = k * check_interval;
+        if (hi > omega) hi = omega;
+        for (int32_t t = 0; t < threads; ++t) {
+            P[t].lo = tau + t;
+            P[t].hi = hi;
+            if (pthread_create(&tid[t], NULL, thread_epoch, &P[t]) != 0) {
+                for (int32_t u = 0; u < t; ++u) pthread_join(tid[u], NULL);
+                rc = -2;
+                goto out;
+            }
+        }
+        for (int32_t t = 0; t < threads; ++t) pthread_join(tid[t], NULL);
+        /* the boundary: every frame into the counters (and zeroed) */
+        for (int32_t t = 0; t < threads; ++t)
+            for (int32_t v = 0; v < n; ++v) {
+                counts[v] += P[t].frame[v];
+                P[t].frame[v] = 0;
+            }
+        tau = hi;
+        st->epochs = k;
+        if (tau == omega) {
+            if (decisions && k - 1 < max_decisions) decisions[k - 1] = 2;
+            break;
+        }
+        int stop = oracle_check_stop(n, counts, tau, omega, L, eps);
+        if (decisions && k - 1 < max_decisions) decisions[k - 1] = (int8_t)stop;
+        if (stop) break;
+    }
+    st->tau = tau;
+    for (int32_t t = 0; t < threads; ++t) {
+        st->v_exp += P[t].st.v_exp;
+        st->e_scan += P[t].st.e_scan;
+        st->v_new += P[t].st.v_new;
+        st->e_pred += P[t].st.e_pred;
+        st->e_bt += P[t].st.e_bt;
+        st->path_interior += P[t].st.path_interior;
+        st->disconnected += P[t].st.disconnected;
+        st->rescaled_levels += P[t].st.rescaled_levels;
+    }
+    rc = 0;
+out:
+    for (int32_t t = 0; t < made; ++t) {
+        sampler_free(&P[t].S);
+        free(P[t].frame);
+        free(P[t].interior);
+    }
+    free(P); free(tid); free(comp);
+    return rc;
 }
 
 /* Single sample, for the path-law and unbiasedness tests.  Returns the number

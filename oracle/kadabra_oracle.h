@@ -75,6 +75,15 @@ int oracle_setup(int32_t n, const int32_t *row_ptr, const int32_t *col, double e
 int oracle_run(int32_t n, const int32_t *row_ptr, const int32_t *col, double eps, double delta,
                uint64_t seed, int64_t check_interval, int64_t sample_cap, int32_t *counts,
                oracle_stats *st, int8_t *decisions, int64_t max_decisions);
+
+/* oracle_run (uniform constants, no sample cap) on `threads` threads: each
+ * epoch's samples are split by index over per-thread counter frames that are
+ * added into the counters at the boundary before the check; the result equals
+ * oracle_run's.  Returns 0, -1 (bad argument) or -2 (allocation or thread
+ * creation failed). */
+int oracle_run_threads(int32_t n, const int32_t *row_ptr, const int32_t *col, double eps, double delta,
+                       uint64_t seed, int64_t check_interval, int32_t threads, int32_t *counts,
+                       oracle_stats *st, int8_t *decisions, int64_t max_decisions);
 int32_t oracle_sample(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *comp,
                       uint64_t seed, uint64_t i, int32_t *interior, oracle_sample_info *info);
 int32_t oracle_sample_pair(int32_t n, const int32_t *row_ptr, const int32_t *col,
