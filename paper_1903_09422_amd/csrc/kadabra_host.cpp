@@ -606,8 +606,9 @@ struct Runner {
     int clear_pool_if_dirty()
     {
         if (!pool_dirty) return KADABRA_OK;
+        // code words start at zero (a sample clears the words it set); sigma
+        // needs no initial value (a sample writes it before reading it)
         HIP_OR_FAIL(kd::launch_fill_u32(st.code, (size_t)slots * st.code_stride, 0u, stream));
-        HIP_OR_FAIL(kd::launch_fill_u32((uint32_t *)st.sigma, (size_t)slots * st.nstride * 8, 0u, stream));
         pool_dirty = false;
         return KADABRA_OK;
     }
@@ -1979,7 +1980,8 @@ int kadabra_run_static(kadabra_graph *g, double eps, double delta, uint64_t seed
     st.code_stride = code_stride_for(gd.n);
     const hipStream_t s = g->runner.stream;
     // the array keeps the last call's contents: clear what must start at zero
-    // (counters, frames, control block and claim counter, code words, sigma)
+    // (counters, frames, control block and claim counter, code words; sigma is
+    // written by a sample before it reads it)
     kd::ZeroRegions z{};
     auto zero = [&](void *ptr, size_t bytes) {
         z.ptr[z.n] = (uint32_t *)ptr;
@@ -1990,7 +1992,6 @@ int kadabra_run_static(kadabra_graph *g, double eps, double delta, uint64_t seed
     zero(ctl, lay.desc - lay.ctl);  // control block and claim counter
     zero(frames, 2 * (size_t)gd.n * sizeof(int32_t));
     zero(st.code, (size_t)slots * (size_t)st.code_stride * sizeof(uint32_t));
-    zero(st.sigma, (size_t)slots * 2 * (size_t)gd.n * sizeof(kd::Sigma));
     HIP_OR_FAIL(kd::launch_zero_regions(z, s));
     // one epoch per launch, checked before the next is queued
     uint64_t claim_next = 0;

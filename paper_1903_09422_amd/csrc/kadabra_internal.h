@@ -51,8 +51,9 @@ struct Control {
 };
 
 // Per-slot sampling state (a pool shared by every query of a launch; a slot
-// holds one sample at a time).  Between samples every code word and every
-// sigma is zero (each sample clears what it touched).
+// holds one sample at a time).  Between samples every code word is zero (each
+// sample clears the words it set); sigma holds stale values, and a sample
+// writes the sigma of each vertex it reaches before reading it.
 struct SlotState {
     uint32_t *code;     // [slots][code_stride] 2-bit level codes per side, 8 vertices a word
     Sigma *sigma;       // [slots][2][nstride] sigma_s, sigma_t

@@ -497,9 +497,11 @@ __device__ __forceinline__ void lds_add128(Sigma *p, Sigma v)
     if (hi) atomicAdd((unsigned long long *)&p->hi, (unsigned long long)hi);
 }
 
-// Zeroes the code word and sigma of every vertex in ball[0, len).
+// Zeroes the code word of every vertex in ball[0, len).  (Sigma needs no
+// clearing: a sample reads it only for vertices it reached, and writes it
+// first for each of them.)
 template <int TEAM>
-__device__ __forceinline__ void clear_ball(const int32_t *ball, int32_t len, uint32_t *code, Sigma *sig)
+__device__ __forceinline__ void clear_ball(const int32_t *ball, int32_t len, uint32_t *code)
 {
     constexpr int U = 4;
     for (int32_t k0 = threadIdx.x; k0 < len; k0 += U * TEAM) {
@@ -508,10 +510,7 @@ __device__ __forceinline__ void clear_ball(const int32_t *ball, int32_t len, uin
         for (int u = 0; u < U; ++u) w[u] = (k0 + u * TEAM < len) ? ball[k0 + u * TEAM] : -1;
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (w[u] >= 0) {
-                code[w[u] >> 3] = 0u;
-                sig[w[u]] = Sigma{0u, 0u};
-            }
+            if (w[u] >= 0) code[w[u] >> 3] = 0u;
     }
 }
 
@@ -823,7 +822,12 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                         }
                         return own;
                     };
-                    for (int32_t e = lane; e < tot; e += PA * TEAM) {
+                    // rounds of PA * TEAM arcs, the same number in every lane: the
+                    // winner of y's claim zeroes sigma_X(y), and the round's adds
+                    // follow a barrier
+                    const int32_t rounds = (tot + PA * TEAM - 1) / (PA * TEAM);
+                    for (int32_t r = 0; r < rounds; ++r) {
+                        const int32_t e = r * PA * TEAM + lane;
                         int32_t ai[PA], yv[PA], pv[PA];
                         uint32_t wd[PA], old[PA];
                         bool hit[PA];
@@ -832,11 +836,11 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                         for (int k = 0; k < PA; ++k) {
                             const int32_t ek = e + k * TEAM;
                             int32_t o = own;
-                            if (k == 0 || ek < tot) {
+                            if (ek < tot) {
                                 o = owner_of(ek);
                                 ai[k] = sm.crs[o] + (ek - sm.cpfx[o]);
                             } else {
-                                ai[k] = ai[0];
+                                ai[k] = 0;  // arc 0 of the graph: the load stays in bounds
                             }
                             yv[k] = (int32_t)(uint32_t)sm.cm[o].lo;
                         }
@@ -846,8 +850,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                         for (int k = 0; k < PA; ++k) wd[k] = code[pv[k] >> 3];
 #pragma unroll
                         for (int k = 0; k < PA; ++k) {
-                            hit[k] = (k == 0 || e + k * TEAM < tot) &&
-                                     ((wd[k] >> code_shift(pv[k], X)) & 3u) == code_front;
+                            hit[k] = e + k * TEAM < tot && ((wd[k] >> code_shift(pv[k], X)) & 3u) == code_front;
                             sp[k] = hit[k] ? sigx[pv[k]] : Sigma{0u, 0u};
                         }
 #pragma unroll
@@ -860,10 +863,12 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                             if (claimed) {
                                 ballx[base_new + pp] = yv[k];
                                 if (pp < STAGE) sm.sv[pp] = yv[k];
+                                sigx[yv[k]] = Sigma{0u, 0u};
                             }
                             const int q = wave_append(claimed, cnt_meet);
                             if (claimed) meet[q] = yv[k];
                         }
+                        __syncthreads();
                         // sigma_X(y) += sigma_X(p)
 #pragma unroll
                         for (int k = 0; k < PA; ++k) {
@@ -930,18 +935,20 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     // ow and add receive the arcs and which of them enter the new level.
                     auto claim_round = [&](int32_t e, int32_t (&wv)[ARCS], int32_t (&ow)[ARCS], bool (&add)[ARCS]) {
                         // owners and arc positions (LDS only); an arc past the end
-                        // repeats arc e so that every load below is unconditional
+                        // reads arc 0 of the graph, so that every load below is
+                        // unconditional (the round loop is the same for every lane,
+                        // so in the last round even a lane's first arc may be past it)
                         int32_t ai[ARCS];
                         uint32_t wd[ARCS];
     #pragma unroll
                         for (int k = 0; k < ARCS; ++k) {
                             const int32_t ek = e + k * TEAM;
-                            if (k == 0 || ek < tot) {
+                            if (ek < tot) {
                                 ow[k] = owner_of(ek);
                                 ai[k] = sm.crs[ow[k]] + (ek - sm.cpfx[ow[k]]);
                             } else {
-                                ow[k] = ow[0];
-                                ai[k] = ai[0];
+                                ow[k] = own;
+                                ai[k] = 0;
                             }
                         }
     #pragma unroll
@@ -956,7 +963,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                         bool cand[ARCS];
     #pragma unroll
                         for (int k = 0; k < ARCS; ++k) {
-                            const bool valid = k == 0 || e + k * TEAM < tot;
+                            const bool valid = e + k * TEAM < tot;
                             dxc[k] = (wd[k] >> code_shift(wv[k], X)) & 3u;
                             dyc[k] = (wd[k] >> code_shift(wv[k], X ^ 1)) & 3u;
                             cand[k] = valid && dxc[k] == 0u && (!probe || dyc[k] != 0u);
@@ -977,12 +984,16 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                             if (claimed) {
                                 ballx[base_new + p] = w;
                                 if (p < STAGE) sm.sv[p] = w;
-                                if (lds_try && p < HMAX) hash_insert(hkeys, HMASK, w);
+                                if (lds_try) {
+                                    if (p < HMAX) hash_insert(hkeys, HMASK, w);
+                                } else {
+                                    sigx[w] = Sigma{0u, 0u};  // summed in global memory below
+                                }
                             }
                             const bool is_meet = claimed && dyc[k] != 0u;
                             const int q = wave_append(is_meet, cnt_meet);
                             if (is_meet) meet[q] = w;
-                            add[k] = (k == 0 || e + k * TEAM < tot) && dxc[k] == code_new;
+                            add[k] = e + k * TEAM < tot && dxc[k] == code_new;
                         }
                     };
                     // sigma(w) += sigma(owner) for every arc into the new level, in
@@ -1015,9 +1026,18 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     bool add[ARCS];
     #pragma unroll
                     for (int k = 0; k < ARCS; ++k) add[k] = false;
-                    for (int32_t e = lane; e < tot; e += ARCS * TEAM) {
-                        claim_round(e, wv, ow, add);
-                        if (!lds_try) global_adds(wv, ow, add);  // else: one round, added below
+                    // rounds of ARCS * TEAM arcs, the same number in every lane.  A
+                    // vertex's sigma is written only by the sample that reaches it
+                    // (nothing clears it afterwards): in global memory the winner of
+                    // its claim zeroes it, and the adds of a round follow a barrier
+                    // after the round's claims.
+                    const int32_t rounds = (tot + ARCS * TEAM - 1) / (ARCS * TEAM);
+                    for (int32_t r = 0; r < rounds; ++r) {
+                        claim_round(r * ARCS * TEAM + lane, wv, ow, add);
+                        if (!lds_try) {  // else: one round, added below
+                            __syncthreads();
+                            global_adds(wv, ow, add);
+                        }
                     }
                     if (lds_try) {
                         __syncthreads();  // the claims are done and the set is filled
@@ -1032,6 +1052,11 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                                     lds_add128(q, sm.cm[ow[k]]);
                             }
                         } else {
+                            // too many new vertices for the set: zero their sigma,
+                            // then add in global memory
+                            for (int32_t k = lane; k < uniform_i32(*cnt_new); k += TEAM)
+                                sigx[ballx[base_new + k]] = Sigma{0u, 0u};
+                            __syncthreads();
                             global_adds(wv, ow, add);
                         }
                     }
@@ -1402,8 +1427,8 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
         // a code word holds only codes of vertices reached by this sample, so
         // zeroing whole words restores the all-zero state; four list entries
         // are loaded before their stores
-        clear_ball<TEAM>(ball0, bend0, code, sig0);
-        clear_ball<TEAM>(ball1, bend1, code, sig1);
+        clear_ball<TEAM>(ball0, bend0, code);
+        clear_ball<TEAM>(ball1, bend1, code);
         PHASE_MARK(5);
     }
     flush();
