@@ -138,6 +138,11 @@ def main() -> int:
     ap.add_argument("--workload", default="rmat18",
                     choices=["rmat18", "pgrid1024", "er4096", "batch64", "serve"])
     ap.add_argument("--serve-queries", type=int, default=256)
+    ap.add_argument("--serve-loads", default="0.5,0.8,1.0",
+                    help="serve: Poisson arrival rates as multiples of the one-at-a-time capacity")
+    ap.add_argument("--round-us", default="",
+                    help="serve: comma-separated round work caps (microseconds, 0 = none) of "
+                         "extra batching servers to compare with the default one")
     ap.add_argument("--no-rmat22", action="store_true",
                     help="serve: leave R-MAT scale 22 out of the graph pool")
     ap.add_argument("--seed", type=int, default=1)
@@ -190,7 +195,7 @@ def main() -> int:
         print(json.dumps(out))
         return 0
     if args.workload == "serve":
-        out = bench_serve(args, (0.5, 0.8, 1.0))
+        out = bench_serve(args, tuple(float(x) for x in args.serve_loads.split(",") if x))
         print(json.dumps(out))
         return 0
 
@@ -509,14 +514,18 @@ def bench_serve(args, loads) -> dict:
 
     out_rates = {}
     legs = {}
-    servers = [("one_at_a_time", 1, 0), ("batching", 0, 0)]
+    servers = [("one_at_a_time", 1, 0, None), ("batching", 0, 0, None)]
     if args.balanced_steps > 0:
-        servers.append(("batching_balanced", 0, 1))
-    for name, max_active, balance in servers:
+        servers.append(("batching_balanced", 0, 1, None))
+    for cap in (int(x) for x in args.round_us.split(",") if x):
+        servers.append((f"batching_round_us_{cap}", 0, 0, cap))
+    for name, max_active, balance, round_us in servers:
         srv = Server(handles, max_active=max_active)
         for k, v in (("team", args.team), ("slots", args.slots), ("probe_min", args.probe_min),
                      ("epochs_per_launch", args.epochs_per_launch), ("balance", balance)):
             srv.set_param(k, v)
+        if round_us is not None:
+            srv.set_param("round_us", round_us)
         replay(srv, None)  # warm-up: pool, buffers, code
         torch.cuda.synchronize()
         tot, span, info = replay(srv, None)

@@ -353,8 +353,16 @@ typedef struct {
 int kadabra_server_create(const kadabra_graph *const *graphs, int32_t ngraphs, int64_t hbm_budget_bytes,
                           int32_t max_active, kadabra_server **out);
 
-/* Mapping parameters as kadabra_batch_set_param; only before the first submit
- * (ESTATE after).  get_param also reads "graphs", "max_active", "budget". */
+/* Mapping parameters as kadabra_batch_set_param, and "round_us": the round
+ * work cap in microseconds (default 16000; 0: none).  Waiting queries are
+ * admitted, in submission order, only while the estimated device time of the
+ * first sampling launches of the admitted, unfinished queries stays within
+ * the cap; a query is always admitted when none runs.  A long query then
+ * shares its launches only with queries submitted before it, and short ones
+ * are batched in short rounds.  The estimates come from one calibration
+ * launch per graph (2048 samples, timed) on the first submission; they never
+ * change a result.  Only before the first submit (ESTATE after).  get_param
+ * also reads "graphs", "max_active", "budget". */
 int kadabra_server_set_param(kadabra_server *s, const char *key, int64_t value);
 int kadabra_server_get_param(const kadabra_server *s, const char *key, int64_t *value);
 

@@ -1150,6 +1150,8 @@ struct Served : Query {
     std::string err;
     std::chrono::steady_clock::time_point t_admit;
     double latency_ms = 0.0;
+    int32_t graph = 0;         // index in the server's graphs
+    double est_ms = 0.0;       // estimated device time of its first sampling launch
 };
 
 struct kadabra_server {
@@ -1177,6 +1179,16 @@ struct kadabra_server {
     int64_t queue_n = 0;
     bool started = false, stop = false;
     bool mapped = false;  // the pool matches params (fixed from the first run on)
+    // Round work cap: queries are admitted (in submission order) only while the
+    // estimated device time of the admitted queries' launches stays within
+    // round_ms, except that a query is always admitted when nothing runs.  A
+    // long query then runs without later arrivals in its launches (as it would
+    // first come first served), and short ones are batched in short rounds.
+    // Estimates come from a calibration launch per graph; they never change a
+    // result.  0: no cap.
+    double round_ms = 16.0;
+    std::vector<double> ms_per_sample;  // per graph, from the calibration
+    double active_est = 0.0;            // sum of est_ms over admitted, unfinished queries
     int broken = KADABRA_OK;
     std::string broken_err;
     std::thread worker;
@@ -1209,7 +1221,15 @@ struct kadabra_server {
     }
     bool can_admit_locked() const
     {
-        return !pending.empty() && active < max_active && in_use + pending.front()->charge <= budget;
+        if (pending.empty() || active >= max_active || in_use + pending.front()->charge > budget) return false;
+        return round_ms <= 0.0 || active == 0 || active_est + pending.front()->est_ms <= round_ms;
+    }
+    // estimated device time of a query's first sampling launch
+    double estimate_ms(const Served &v) const
+    {
+        if ((size_t)v.graph >= ms_per_sample.size()) return 0.0;
+        const int64_t first = std::min<int64_t>((int64_t)params.epochs * v.N, v.omega) + v.m1;
+        return (double)first * ms_per_sample[(size_t)v.graph];
     }
     // Moves admissible queries (in submission order) to out; buffers that no
     // longer fit next to the admitted ones are handed back in to_free.
@@ -1220,6 +1240,8 @@ struct kadabra_server {
             pending.pop_front();
             const size_t n = (size_t)v->gd->n;
             v->admitted = true;
+            v->est_ms = estimate_ms(*v);
+            active_est += v->est_ms;
             v->t_admit = std::chrono::steady_clock::now();
             queue_ms_sum += std::chrono::duration<double, std::milli>(v->t_admit - v->t_submit).count();
             queue_n += 1;
@@ -1429,6 +1451,39 @@ int autotune(Runner &R, std::vector<Query *> &qs, Params &p, int64_t trial_sampl
     return KADABRA_OK;
 }
 
+// Device time per sample of each of the server's graphs: one launch of a
+// fixed number of samples (a calibration seed, no checks) per graph, on the
+// server's pool and mapping, after one warm-up launch.  Only admission uses
+// it.  The estimates of pending queries are filled in.
+int calibrate_server(kadabra_server *s)
+{
+    if (!s->mapped) {
+        int tm;
+        int64_t sl;
+        s->runner.choose_mapping(s->params, s->nmax, s->lcap, &tm, &sl);
+        OK_OR_RETURN(s->runner.ensure_pool(tm, sl, s->nmax, s->lcap, nullptr));
+        s->mapped = true;
+    }
+    std::vector<double> ms(s->graphs.size(), 0.0);
+    Params p = s->params;
+    p.balance = 0;
+    for (size_t g = 0; g < s->graphs.size(); ++g) {
+        Query q;
+        OK_OR_RETURN(make_query(q, *s->graphs[g], p, 0.01, 0.1, 0xCA11B8A7Eull, 1 << 30));
+        const int64_t trial = std::min<int64_t>(2048, q.omega);
+        for (int rep = 0; rep < (g == 0 ? 2 : 1); ++rep) {
+            std::vector<Query *> qs{&q};
+            const auto t0 = std::chrono::steady_clock::now();
+            OK_OR_RETURN(s->runner.run(qs, p, nullptr, trial, nullptr, nullptr));
+            ms[g] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() /
+                    (double)trial;
+        }
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->ms_per_sample = ms;
+    return KADABRA_OK;
+}
+
 // The server's worker: waits for submissions, then runs the round loop for
 // as long as any query is active, admitting new ones at every boundary.
 void server_main(kadabra_server *s)
@@ -1446,6 +1501,7 @@ void server_main(kadabra_server *s)
         s->lat.push_back(v->latency_ms);
         s->completed += 1;
         s->active -= 1;
+        s->active_est = s->active > 0 ? std::max(0.0, s->active_est - v->est_ms) : 0.0;
         // the frames are free once the last merge has run (an epoch queued
         // speculatively for this query exits on the device without writing)
         s->put_bin(v->frames, v->frames_len * sizeof(int32_t));
@@ -1472,6 +1528,19 @@ void server_main(kadabra_server *s)
     for (;;) {
         std::vector<Query *> first;
         std::vector<void *> to_free;
+        if (s->ms_per_sample.empty() && s->round_ms > 0.0) {
+            // wait for the first submission (parameters are fixed from then
+            // on), then time a short calibration launch per graph
+            {
+                std::unique_lock<std::mutex> lk(s->mu);
+                s->cv_work.wait(lk, [s] { return s->stop || !s->pending.empty(); });
+                if (s->stop) break;
+            }
+            if (calibrate_server(s) != KADABRA_OK) {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->round_ms = 0.0;  // no estimates: admit without the cap
+            }
+        }
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_work.wait(lk, [s] { return s->stop || s->can_admit_locked(); });
@@ -2285,6 +2354,11 @@ int kadabra_server_set_param(kadabra_server *s, const char *key, int64_t value)
     if (s->started) return fail(KADABRA_ESTATE, "parameters are fixed once a query was submitted");
     if (!strcmp(key, "check_interval")) return fail(KADABRA_EINVAL, "check_interval is set per query");
     if (!strcmp(key, "test_fail_alloc")) return fail(KADABRA_EINVAL, "test_fail_alloc is not supported here");
+    if (!strcmp(key, "round_us")) {
+        if (value < 0 || value > (int64_t)1e9) return fail(KADABRA_EINVAL, "round_us must be in [0, 1e9]");
+        s->round_ms = (double)value * 1e-3;
+        return KADABRA_OK;
+    }
     bool known;
     OK_OR_RETURN(set_common_param(s->params, key, value, &known));
     if (!known) return fail(KADABRA_EINVAL, "unknown parameter '%s'", key);
@@ -2299,6 +2373,7 @@ int kadabra_server_get_param(const kadabra_server *s, const char *key, int64_t *
     if (!strcmp(key, "graphs")) *value = (int64_t)s->graphs.size();
     else if (!strcmp(key, "max_active")) *value = s->max_active;
     else if (!strcmp(key, "budget")) *value = s->budget;
+    else if (!strcmp(key, "round_us")) *value = (int64_t)std::llround(s->round_ms * 1e3);
     else return fail(KADABRA_EINVAL, "unknown parameter '%s'", key);
     return KADABRA_OK;
 }
@@ -2317,6 +2392,7 @@ int kadabra_server_submit(kadabra_server *s, int32_t graph_index, double eps, do
     if (!v) return fail(KADABRA_ENOMEM, "host allocation failed");
     const GraphData &gd = *s->graphs[(size_t)graph_index];
     OK_OR_RETURN(make_query(*v, gd, s->params, eps, delta, seed, check_interval));
+    v->graph = graph_index;
     v->charge = s->charge_of(*v);
     v->frame_bytes = s->frame_bytes_of(*v);
     if (v->charge > s->budget)

@@ -42,15 +42,21 @@ def _charge(n, frames=1, epochs=2):
     return n * (4 + 8 + 8 * epochs * frames)
 
 
-def test_serve_staggered_equals_oracle():
+@pytest.mark.parametrize("round_us", [None, 0, 1, 300])
+def test_serve_staggered_equals_oracle(round_us):
     """Queries arrive while others run (two submitting threads, random gaps);
-    every result equals the oracle's."""
-    print("case serve staggered mix", flush=True)
+    every result equals the oracle's, whatever the round work cap (the
+    default, none, one that admits a query only when none runs, and a small
+    one)."""
+    print(f"case serve staggered mix, round_us={round_us}", flush=True)
     handles = [Graph.from_csr(g) for g, *_ in MIX]
     jobs = [(k, seed) for seed in (3, 4) for k in range(len(MIX))]
     tickets = {}
     lock = threading.Lock()
     with Server(handles) as srv:
+        if round_us is not None:
+            srv.set_param("round_us", round_us)
+        assert srv.get_param("round_us") == (16000 if round_us is None else round_us)
         def submitter(part, rng_seed):
             rng = np.random.default_rng(rng_seed)
             for k, seed in part:
