@@ -576,17 +576,20 @@ def bench_serve(args, loads) -> dict:
 COPY_BYTES = 1 << 30
 PMC_CMDS = {
     "trace": "rocprofv3 --kernel-trace --stats -f csv -d DIR/ktrace -o bench -- "
-             "python3 bench.py --workload {w} --steps 5 --warmup 1 --no-cpu --balanced-steps 0",
+             "python3 bench.py --workload {w} --steps 5 --warmup 1 --no-cpu --balanced-steps 0 --legs ''",
     "fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d DIR/pmc_FETCH_SIZE -o bench -- "
-             "python3 bench.py --workload {w} --steps 2 --warmup 0 --no-cpu --balanced-steps 0",
+             "python3 bench.py --workload {w} --steps 2 --warmup 0 --no-cpu --balanced-steps 0 --legs ''",
     "write": "rocprofv3 --pmc WRITE_SIZE -f csv -d DIR/pmc_WRITE_SIZE -o bench -- "
-             "python3 bench.py --workload {w} --steps 2 --warmup 0 --no-cpu --balanced-steps 0",
+             "python3 bench.py --workload {w} --steps 2 --warmup 0 --no-cpu --balanced-steps 0 --legs ''",
     "copy_fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d DIR/pmc_copy_FETCH_SIZE -o copy -- "
                   "python3 bench.py --calibrate-copy 1073741824",
     "copy_write": "rocprofv3 --pmc WRITE_SIZE -f csv -d DIR/pmc_copy_WRITE_SIZE -o copy -- "
                   "python3 bench.py --calibrate-copy 1073741824",
     "l2": "rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum -f csv -d DIR/pmc_tcc -o bench -- "
-          "python3 bench.py --workload {w} --steps 2 --warmup 0 --no-cpu --balanced-steps 0",
+          "python3 bench.py --workload {w} --steps 2 --warmup 0 --no-cpu --balanced-steps 0 --legs ''",
+    "wrreq": "rocprofv3 --pmc TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum TCC_EA0_RDREQ_sum "
+             "TCC_EA0_RDREQ_DRAM_sum -f csv -d DIR/pmc_ea -o bench -- "
+             "python3 bench.py --workload {w} --steps 2 --warmup 0 --no-cpu --balanced-steps 0 --legs ''",
 }
 
 
@@ -631,9 +634,27 @@ def ingest_pmc(d: str, workload: str) -> int:
             h = float(np.mean([v["TCC_HIT_sum"] for v in full_l2]))
             m = float(np.mean([v["TCC_MISS_sum"] for v in full_l2]))
             l2 = {"hits_per_launch": h, "misses_per_launch": m, "hit_rate": h / (h + m)}
+    # the write bytes again from the L2-to-memory write requests (32 or 64
+    # bytes each), beside WRITE_SIZE, and the share of L2 read misses that
+    # went to DRAM
+    ea = None
+    if os.path.isdir(os.path.join(d, "pmc_ea")):
+        by = {}
+        for r in rows(os.path.join(d, "pmc_ea", "bench_counter_collection.csv")):
+            if "sample_kernel" in r["Kernel_Name"]:
+                by.setdefault(r["Dispatch_Id"], {})[r["Counter_Name"]] = float(r["Counter_Value"])
+        full_ea = [v for v in by.values() if v.get("TCC_EA0_RDREQ_sum", 0) > 1e5]
+        if full_ea:
+            wr = float(np.mean([v["TCC_EA0_WRREQ_sum"] for v in full_ea]))
+            w64 = float(np.mean([v["TCC_EA0_WRREQ_64B_sum"] for v in full_ea]))
+            rd = float(np.mean([v["TCC_EA0_RDREQ_sum"] for v in full_ea]))
+            rdd = float(np.mean([v["TCC_EA0_RDREQ_DRAM_sum"] for v in full_ea]))
+            ea = {"write_requests": wr, "write_requests_64B": w64,
+                  "write_bytes": 64.0 * w64 + 32.0 * (wr - w64), "read_requests": rd,
+                  "read_requests_dram": rdd, "dram_share_of_reads": rdd / rd if rd else None}
     summary = {
         "kernel": "sample_kernel", "workload": workload, "kernel_source_sha": _kernel_sha(),
-        "l2": l2,
+        "l2": l2, "ea": ea,
         "hbm_bytes_per_launch": hbm,
         "fetch_kib_per_launch": float(np.mean(fetch)), "write_kib_per_launch": float(np.mean(write)),
         "fetch_factor": fetch_factor, "write_factor": write_factor,
@@ -663,6 +684,15 @@ def ingest_pmc(d: str, workload: str) -> int:
         f.write(f"- WRITE_SIZE per sampling launch: {np.mean(write):.0f} KiB; calibration factor "
                 f"{write_factor:.3f}\n")
         f.write(f"- HBM bytes per launch: {hbm / 1e9:.3f} GB\n")
+        if ea:
+            f.write("\n## L2 to memory requests (--pmc TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum "
+                    "TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_DRAM_sum)\n\n")
+            f.write(f"- write requests per sampling launch: {ea['write_requests']:.4g} "
+                    f"({ea['write_requests_64B']:.4g} of 64 bytes, the rest 32): "
+                    f"{ea['write_bytes'] / 1e9:.3f} GB written, against WRITE_SIZE's "
+                    f"{np.mean(write) * 1024 * write_factor / 1e9:.3f} GB\n")
+            f.write(f"- read requests: {ea['read_requests']:.4g}, of which to DRAM "
+                    f"{ea['read_requests_dram']:.4g}\n")
         if l2:
             f.write("\n## L2 (--pmc TCC_HIT_sum TCC_MISS_sum)\n\n")
             f.write(f"- per sampling launch: {l2['hits_per_launch']:.4g} hits, "
