@@ -99,6 +99,21 @@ typedef struct {
 int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr,
                          const int32_t *col_idx, kadabra_graph **out);
 
+/* A consistent state of an adaptive run at a check boundary (Algorithm 1:
+ * the counters of exactly samples [0, tau), every boundary so far decided
+ * "continue"), from which kadabra_resume continues to the same result as an
+ * uninterrupted run (sample i depends on i alone; Appendix D). */
+typedef struct {
+    int64_t n;              /* vertices: the length of the counters */
+    int64_t tau;            /* samples in the counters: a check boundary below omega */
+    int64_t epochs;         /* boundaries checked so far */
+    int64_t omega;
+    int64_t check_interval;
+    double eps, delta;
+    uint64_t seed;
+    int64_t work[6];        /* v_exp, e_scan, e_bt, path_interior, disconnected, v_written so far */
+} kadabra_checkpoint;
+
 /*
  * Sets a run parameter; it applies to the next kadabra_run.
  *   "check_interval"  N >= 1: the stopping rule is checked after every N
@@ -144,6 +159,12 @@ int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr,
  *                     Default 0.
  *   "test_fail_alloc" k >= 1: the k-th device allocation of the next run's
  *                     buffers fails with ENOMEM (failure-path testing); 0: off.
+ *   "stop_after_epochs" k >= 1: the run stops at the end of the first round
+ *                     (one sampling launch and its checks) after k boundaries
+ *                     of this run, if it has not stopped by itself, and
+ *                     returns ECANCELED with a checkpoint readable by
+ *                     kadabra_get_checkpoint; 0 (default): off.  Uniform
+ *                     constants only ("balance" = 0).
  *   "test_level_cap"  k >= 3: the sampler is given room for only k BFS levels
  *                     per side, so samples needing more fail its level-bound
  *                     check and the run ends with EDEVICE (failure-path
@@ -210,6 +231,30 @@ int kadabra_run(kadabra_graph *g, double eps, double delta, uint64_t seed);
  */
 int kadabra_run_static(kadabra_graph *g, double eps, double delta, uint64_t seed, int32_t *counts_dev,
                        kadabra_stats *stats);
+
+/*
+ * The state of the last run when it stopped at a boundary ("stop_after_epochs",
+ * or kadabra_cancel: both stop at the end of a round, whose boundaries were
+ * all decided "continue"): *ck, and counts (host int32[n], or NULL) the
+ * counters of samples [0, ck->tau), in the given vertex order.  The state may
+ * be stored and handed to kadabra_resume on any handle of the same graph, in
+ * this process or another.  Errors: ESTATE (the last run completed, failed
+ * otherwise, or was balanced), EINVAL, EDEVICE.
+ */
+int kadabra_get_checkpoint(const kadabra_graph *g, kadabra_checkpoint *ck, int32_t *counts);
+
+/*
+ * Continues a run from a checkpoint to completion (blocking): the result
+ * (tau, every counter, the decisions of every boundary, the work counters)
+ * equals the uninterrupted kadabra_run(ck->eps, ck->delta, ck->seed) with
+ * check interval ck->check_interval.  counts: host int32[n] as returned by
+ * kadabra_get_checkpoint (read during the call only).  Mapping parameters of
+ * g apply; "stop_after_epochs" may stop it again.  Errors: EINVAL (a
+ * checkpoint that does not fit this graph: n, omega, tau not a boundary
+ * before omega, counters out of range or not summing to the increments;
+ * "balance" set), ENOMEM, EDEVICE, ECANCELED.
+ */
+int kadabra_resume(kadabra_graph *g, const kadabra_checkpoint *ck, const int32_t *counts);
 
 /*
  * Reads the last completed run into caller-allocated host memory; any

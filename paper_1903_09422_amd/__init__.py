@@ -18,7 +18,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from ._lib import EXPORTS, KadabraError, ServerInfo, Stats, check, lib  # noqa: F401
+from ._lib import EXPORTS, Checkpoint, KadabraError, ServerInfo, Stats, check, lib  # noqa: F401
 
 __all__ = ["Graph", "Batch", "Server", "RunResult", "KadabraError", "eval_stop_fg", "lib"]
 
@@ -85,6 +85,19 @@ class Graph:
         st = Stats()
         check(lib().kadabra_run_static(self._h, float(eps), float(delta), int(seed), ptr, C.byref(st)))
         return st.as_dict()
+
+    def checkpoint(self):
+        """(Checkpoint, counters) of the last run when it stopped at a
+        boundary ("stop_after_epochs" or cancel)."""
+        ck = Checkpoint()
+        counts = np.empty(self.n, dtype=np.int32)
+        check(lib().kadabra_get_checkpoint(self._h, C.byref(ck), counts.ctypes.data))
+        return ck, counts
+
+    def resume(self, ck, counts) -> None:
+        """Continue a run from a checkpoint to completion (kadabra_resume)."""
+        c = np.ascontiguousarray(counts, dtype=np.int32)
+        check(lib().kadabra_resume(self._h, C.byref(ck), c.ctypes.data))
 
     def cancel(self) -> None:
         check(lib().kadabra_cancel(self._h))

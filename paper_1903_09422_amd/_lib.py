@@ -20,7 +20,7 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE"
 # every symbol declared in include/kadabra.h
 EXPORTS = (
     "kadabra_create_graph", "kadabra_set_param", "kadabra_get_param", "kadabra_set_stream",
-    "kadabra_run", "kadabra_run_static", "kadabra_get_scores", "kadabra_get_scores_device", "kadabra_get_decisions",
+    "kadabra_run", "kadabra_run_static", "kadabra_get_checkpoint", "kadabra_resume", "kadabra_get_scores", "kadabra_get_scores_device", "kadabra_get_decisions",
     "kadabra_get_balance", "kadabra_eval_stop_fg", "kadabra_cancel", "kadabra_destroy_graph", "kadabra_last_error",
     "kadabra_version", "kadabra_autotune", "kadabra_batch_create", "kadabra_batch_set_param",
     "kadabra_batch_get_param", "kadabra_batch_set_stream", "kadabra_batch_add", "kadabra_batch_run",
@@ -52,6 +52,11 @@ class Stats(C.Structure):
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Checkpoint(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("n", "tau", "epochs", "omega", "check_interval")] + [
+        ("eps", C.c_double), ("delta", C.c_double), ("seed", C.c_uint64), ("work", C.c_int64 * 6)]
 
 
 class ServerInfo(C.Structure):
@@ -91,6 +96,8 @@ def lib() -> C.CDLL:
     L.kadabra_set_stream.argtypes = [vp, vp]
     L.kadabra_run.argtypes = [vp, C.c_double, C.c_double, C.c_uint64]
     L.kadabra_run_static.argtypes = [vp, C.c_double, C.c_double, C.c_uint64, vp, C.POINTER(Stats)]
+    L.kadabra_get_checkpoint.argtypes = [vp, C.POINTER(Checkpoint), vp]
+    L.kadabra_resume.argtypes = [vp, C.POINTER(Checkpoint), vp]
     L.kadabra_get_scores.argtypes = [vp, vp, vp, C.POINTER(Stats)]
     L.kadabra_get_scores_device.argtypes = [vp, vp, vp]
     L.kadabra_get_decisions.argtypes = [vp, vp, C.c_int64, i64p]

@@ -204,6 +204,7 @@ struct Params {
     int64_t balance_samples = 0;  // first-phase samples; 0: ceil(omega / 20)
     int64_t fail_alloc = 0;  // test hook
     int32_t level_cap = 0;   // test hook: 0, or a smaller level capacity per side
+    int64_t stop_after = 0;  // > 0: stop at the first round end after this many boundaries of the run
 };
 
 int set_common_param(Params &p, const char *key, int64_t value, bool *known)
@@ -245,6 +246,9 @@ int set_common_param(Params &p, const char *key, int64_t value, bool *known)
     } else if (!strcmp(key, "test_fail_alloc")) {
         if (value < 0) return fail(KADABRA_EINVAL, "test_fail_alloc must be >= 0");
         p.fail_alloc = value;
+    } else if (!strcmp(key, "stop_after_epochs")) {
+        if (value < 0) return fail(KADABRA_EINVAL, "stop_after_epochs must be >= 0");
+        p.stop_after = value;
     } else if (!strcmp(key, "test_level_cap")) {
         if (value != 0 && (value < 3 || value > (1 << 20)))
             return fail(KADABRA_EINVAL, "test_level_cap must be 0 or in [3, 2^20]");
@@ -268,6 +272,7 @@ int get_common_param(const Params &p, const char *key, int64_t *value)
     else if (!strcmp(key, "balance")) *value = p.balance;
     else if (!strcmp(key, "balance_samples")) *value = p.balance_samples;
     else if (!strcmp(key, "test_level_cap")) *value = p.level_cap;
+    else if (!strcmp(key, "stop_after_epochs")) *value = p.stop_after;
     else return 1;
     return 0;
 }
@@ -480,6 +485,12 @@ struct Query {
     std::vector<double> h_lcon;   // the constant table (read by the copy to the device)
     double ms_kernels = 0.0;    // sampler launches that did this query's work
     int64_t launches = 0;
+    // resuming from a checkpoint: the counters of samples [0, resume_tau) (host),
+    // resume_k boundaries already checked, the work counters so far
+    const int32_t *resume_counts = nullptr;
+    int64_t resume_k = 0, resume_tau = 0;
+    int64_t resume_work[kd::ST_COUNT] = {};
+    bool checkpointed = false;  // stopped at a boundary with the counters of [0, tau)
     std::chrono::steady_clock::time_point t_submit, t_done;
 
     int64_t bound(int64_t epoch) const { return std::min<int64_t>(epoch * N, omega); }
@@ -743,6 +754,14 @@ int Runner::start_query(Query &q, int64_t *fc)
     }
     HIP_OR_FAIL(kd::launch_zero_regions(z, stream));
     q.k = q.merged = q.merged_prev = q.lo = 0;
+    q.checkpointed = false;
+    if (q.resume_counts) {
+        // after the zero fill in stream order: the counters and work so far
+        HIP_OR_FAIL(hipMemcpyAsync(q.counts, q.resume_counts, n * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+        HIP_OR_FAIL(hipMemcpyAsync(d_ctl[q.cslot].stats_total, q.resume_work, sizeof q.resume_work,
+                                   hipMemcpyHostToDevice, stream));
+        HIP_OR_FAIL(hipStreamSynchronize(stream));  // the host arrays may go away after the call
+    }
     q.spec = false;
     q.first_launched = false;
     q.plan_tau = 0;
@@ -755,6 +774,12 @@ int Runner::start_query(Query &q, int64_t *fc)
     q.ms_kernels = 0.0;
     q.launches = 0;
     for (auto &w : q.work) w = 0;
+    if (q.resume_counts) {
+        q.k = q.merged = q.merged_prev = q.resume_k;
+        q.lo = q.resume_tau;
+        q.tau = q.resume_tau;
+        q.decisions.assign((size_t)q.resume_k, (int8_t)0);
+    }
     return KADABRA_OK;
 }
 
@@ -1063,6 +1088,14 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
                     q->decisions.push_back((int8_t)dec);
                 }
             }
+            if (dec == 0 && q->status == KADABRA_OK && p.stop_after > 0 && sample_cap < 0 && q->m1 == 0 &&
+                (int64_t)q->decisions.size() - q->resume_k >= p.stop_after) {
+                // stop here with a consistent state: every merged boundary was
+                // decided "continue", so the counters hold exactly [0, tau)
+                q->status = fail(KADABRA_ECANCELED, "stopped after %lld boundaries at %lld samples (checkpoint)",
+                                 (long long)q->decisions.size(), (long long)q->tau);
+                q->checkpointed = true;
+            }
             if (dec || q->status != KADABRA_OK) {
                 q->decision = dec;
                 for (int w = 0; w < kd::ST_COUNT; ++w) q->work[w] = c.stats_total[w];
@@ -1081,6 +1114,11 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
         if (cancel.load() && status == KADABRA_OK) {
             for (Query *q : still) {
                 q->status = fail(KADABRA_ECANCELED, "run canceled at %lld samples", (long long)q->tau);
+                // the boundaries of this round were all decided "continue": a
+                // consistent state to resume from (uniform constants only)
+                const kd::Control &c = h_ctl[q->cslot];
+                for (int w = 0; w < kd::ST_COUNT; ++w) q->work[w] = c.stats_total[w];
+                q->checkpointed = q->m1 == 0 && sample_cap < 0;
                 finished.push_back(q);
             }
             still.clear();
@@ -1878,9 +1916,71 @@ int kadabra_run(kadabra_graph *g, double eps, double delta, uint64_t seed)
     const auto t0 = std::chrono::steady_clock::now();
     g->have_result = false;
     OK_OR_RETURN(ensure_graph_query(g, eps, delta, seed));
+    g->q.resume_counts = nullptr;
+    g->q.resume_k = g->q.resume_tau = 0;
     std::vector<Query *> qs{&g->q};
     OK_OR_RETURN(run_queries(g->runner, qs, g->params));
     if (g->q.status != KADABRA_OK) return g->q.status;
+    g->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    g->have_result = true;
+    return KADABRA_OK;
+}
+
+int kadabra_get_checkpoint(const kadabra_graph *g, kadabra_checkpoint *ck, int32_t *counts)
+{
+    if (!g || !ck) return fail(KADABRA_EINVAL, "null argument");
+    const Query &q = g->q;
+    if (g->have_result || !q.checkpointed || !q.counts)
+        return fail(KADABRA_ESTATE, "the last run did not stop at a boundary");
+    memset(ck, 0, sizeof *ck);
+    ck->n = g->gd.n;
+    ck->tau = q.tau;
+    ck->epochs = (int64_t)q.decisions.size();
+    ck->omega = q.omega;
+    ck->check_interval = q.N;
+    ck->eps = q.eps;
+    ck->delta = q.delta;
+    ck->seed = q.seed;
+    static_assert(kd::ST_COUNT == 6, "checkpoint work counters");
+    for (int w = 0; w < kd::ST_COUNT; ++w) ck->work[w] = q.work[w];
+    if (counts) {
+        HIP_OR_FAIL(hipMemcpyAsync(counts, q.counts, (size_t)g->gd.n * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                   g->runner.stream));
+        HIP_OR_FAIL(hipStreamSynchronize(g->runner.stream));
+    }
+    return KADABRA_OK;
+}
+
+int kadabra_resume(kadabra_graph *g, const kadabra_checkpoint *ck, const int32_t *counts)
+{
+    if (!g || !ck || !counts) return fail(KADABRA_EINVAL, "null argument");
+    g->runner.cancel.store(0);
+    g_last_error.clear();
+    const auto t0 = std::chrono::steady_clock::now();
+    g->have_result = false;
+    if (g->params.balance) return fail(KADABRA_EINVAL, "a balanced run cannot be resumed (balance = 0)");
+    if (ck->n != g->gd.n) return fail(KADABRA_EINVAL, "checkpoint of a graph of %lld vertices", (long long)ck->n);
+    OK_OR_RETURN(make_query(g->q, g->gd, g->params, ck->eps, ck->delta, ck->seed, ck->check_interval));
+    Query &q = g->q;
+    if (q.omega != ck->omega) return fail(KADABRA_EINVAL, "checkpoint omega %lld, this graph gives %lld",
+                                          (long long)ck->omega, (long long)q.omega);
+    if (ck->epochs < 1 || ck->tau != q.bound(ck->epochs) || ck->tau >= q.omega)
+        return fail(KADABRA_EINVAL, "checkpoint at %lld samples is not a boundary before omega", (long long)ck->tau);
+    int64_t total = 0;
+    for (int64_t v = 0; v < ck->n; ++v) {
+        if (counts[v] < 0 || counts[v] > ck->tau) return fail(KADABRA_EINVAL, "counter %lld out of range", (long long)v);
+        total += counts[v];
+    }
+    if (total != ck->work[kd::ST_INTERIOR]) return fail(KADABRA_EINVAL, "counters do not sum to the increments");
+    q.resume_counts = counts;
+    q.resume_k = ck->epochs;
+    q.resume_tau = ck->tau;
+    for (int w = 0; w < kd::ST_COUNT; ++w) q.resume_work[w] = ck->work[w];
+    std::vector<Query *> qs{&q};
+    const int rc = run_queries(g->runner, qs, g->params);
+    q.resume_counts = nullptr;
+    OK_OR_RETURN(rc);
+    if (q.status != KADABRA_OK) return q.status;
     g->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     g->have_result = true;
     return KADABRA_OK;
