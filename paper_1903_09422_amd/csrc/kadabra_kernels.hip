@@ -688,8 +688,6 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 code[s >> 3] = cs0;
                 code[t >> 3] = ct1;
             }
-            sig0[s] = Sigma{1u, 0u};
-            sig1[t] = Sigma{1u, 0u};
             ball0[0] = s;
             ball1[0] = t;
             loff0[0] = 0;
@@ -766,7 +764,13 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
             // in the level's chain of global accesses.  Otherwise the arcs kept
             // in registers add into global memory as usual.  Not on probe levels
             // (a retry reads the cache again) nor when the level may rescale.
-            const bool lds_try = !probe && fhix - flox <= TEAM && dsx <= (int64_t)ARCS * TEAM &&
+            // A vertex one arc from its root has exactly one shortest path from
+            // it, and the root itself one: sigma of levels 0 and 1 is 1, never
+            // stored nor read (on low-diameter graphs most new vertices lie on
+            // level 1 of one side).
+            const bool implicit_new = lvlx == 0;    // the new level is level 1
+            const bool implicit_front = lvlx <= 1;  // the frontier's sigma is 1
+            const bool lds_try = !probe && !implicit_new && fhix - flox <= TEAM && dsx <= (int64_t)ARCS * TEAM &&
                                  bitw128(X ? fmass1 : fmass0) <= SIGMA_BITS;
             const bool low_mass = bitw128(X ? fmass1 : fmass0) <= 63;
             int32_t *const hkeys = reinterpret_cast<int32_t *>(&sm.fsg[X][0]);  // 4 TEAM >= STAGE ints
@@ -851,7 +855,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
 #pragma unroll
                         for (int k = 0; k < PA; ++k) {
                             hit[k] = e + k * TEAM < tot && ((wd[k] >> code_shift(pv[k], X)) & 3u) == code_front;
-                            sp[k] = hit[k] ? sigx[pv[k]] : Sigma{0u, 0u};
+                            sp[k] = !hit[k] ? Sigma{0u, 0u} : (implicit_front ? Sigma{1u, 0u} : sigx[pv[k]]);
                         }
 #pragma unroll
                         for (int k = 0; k < PA; ++k)
@@ -863,11 +867,12 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                             if (claimed) {
                                 ballx[base_new + pp] = yv[k];
                                 if (pp < STAGE) sm.sv[pp] = yv[k];
-                                sigx[yv[k]] = Sigma{0u, 0u};
+                                if (!implicit_new) sigx[yv[k]] = Sigma{0u, 0u};
                             }
                             const int q = wave_append(claimed, cnt_meet);
                             if (claimed) meet[q] = yv[k];
                         }
+                        if (implicit_new) continue;  // sigma_X(y) is 1
                         __syncthreads();
                         // sigma_X(y) += sigma_X(p)
 #pragma unroll
@@ -898,7 +903,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                             const int32_t rs = row_ptr[u];
                             dg = row_ptr[u + 1] - rs;
                             sm.crs[lane] = rs;
-                            sm.cm[lane] = sigx[u];
+                            sm.cm[lane] = implicit_front ? Sigma{1u, 0u} : sigx[u];
                         }
                     }
                     if (lds_try) {
@@ -986,7 +991,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                                 if (p < STAGE) sm.sv[p] = w;
                                 if (lds_try) {
                                     if (p < HMAX) hash_insert(hkeys, HMASK, w);
-                                } else {
+                                } else if (!implicit_new) {
                                     sigx[w] = Sigma{0u, 0u};  // summed in global memory below
                                 }
                             }
@@ -1034,7 +1039,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     const int32_t rounds = (tot + ARCS * TEAM - 1) / (ARCS * TEAM);
                     for (int32_t r = 0; r < rounds; ++r) {
                         claim_round(r * ARCS * TEAM + lane, wv, ow, add);
-                        if (!lds_try) {  // else: one round, added below
+                        if (!lds_try && !implicit_new) {  // else: one round, added below, or sigma 1
                             __syncthreads();
                             global_adds(wv, ow, add);
                         }
@@ -1142,8 +1147,8 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 const int32_t rs = row_ptr[w], re = row_ptr[w + 1];
                 const int32_t rs2 = row_ptr[w2], re2 = row_ptr[w2 + 1];
                 // (an LDS-summed level has nN <= 2 TEAM: k = lane, k2 = lane + TEAM)
-                const Sigma m = lds_sig ? lm0 : sigx[w];
-                const Sigma m2 = lds_sig ? lm1 : sigx[w2];
+                const Sigma m = implicit_new ? Sigma{1u, 0u} : (lds_sig ? lm0 : sigx[w]);
+                const Sigma m2 = implicit_new ? Sigma{1u, 0u} : (lds_sig ? lm1 : sigx[w2]);
                 const int32_t dg = re - rs;
                 ds += (uint64_t)dg;
                 ms += to128(m);
@@ -1181,6 +1186,13 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
 
         if (ok) {
             // -- meeting vertex: P(v) = sigma_s(v) sigma_t(v), ascending id ----
+            // the meeting vertices' distances: one more than side X's frontier
+            // level, side Y's level (sigma 1 on levels 0 and 1)
+            const int32_t dv0 = (X == 0) ? lvl0 + 1 : lvl0;
+            const int32_t dv1 = (X == 1) ? lvl1 + 1 : lvl1;
+            auto sig_of = [&](const Sigma *sg, int32_t dist, int32_t w) -> u128 {
+                return dist <= 1 ? (u128)1 : to128(sg[w]);
+            };
             int32_t v;
             if (nM == 1) {
                 v = meet_staged ? sm.sv[0] : meet[0];
@@ -1193,7 +1205,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 if (has) {
                     w = meet_staged ? sm.sv[lane] : meet[lane];
                     wo = (MAPPED && qd->iperm) ? qd->iperm[w] : w;
-                    p = mul_128x128(to128(sig0[w]), to128(sig1[w]));
+                    p = mul_128x128(sig_of(sig0, dv0, w), sig_of(sig1, dv1, w));
                 }
                 const U256 pm = T::max_u256(p, redA);
                 const int shp = max(0, bitw256(pm) - WEIGHT_BITS);
@@ -1219,7 +1231,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 U256 pm{0, 0};
                 for (int32_t k = lane; k < nM; k += TEAM) {
                     const int32_t w = meet[k];
-                    const U256 p = mul_128x128(to128(sig0[w]), to128(sig1[w]));
+                    const U256 p = mul_128x128(sig_of(sig0, dv0, w), sig_of(sig1, dv1, w));
                     if (p.hi > pm.hi || (p.hi == pm.hi && p.lo > pm.lo)) pm = p;
                 }
                 pm = T::max_u256(pm, redA);
@@ -1230,7 +1242,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     const int32_t w = meet[k];
                     const int32_t wo = (MAPPED && qd->iperm) ? qd->iperm[w] : w;  // ranked by original id
                     const uint64_t wt =
-                        ceil_shr256(mul_128x128(to128(sig0[w]), to128(sig1[w])), shp);
+                        ceil_shr256(mul_128x128(sig_of(sig0, dv0, w), sig_of(sig1, dv1, w)), shp);
                     if (staged) {
                         sm.sv[k] = wo;
                         sm.sw[k] = Sigma{wt, 0u};
@@ -1284,9 +1296,6 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 v = (MAPPED && qd->perm) ? qd->perm[lo] : lo;
             }
             PHASE_MARK(3);
-            // v's distances: one more than side X's frontier level, side Y's level
-            const int32_t dv0 = (X == 0) ? lvl0 + 1 : lvl0;
-            const int32_t dv1 = (X == 1) ? lvl1 + 1 : lvl1;
             if (lane == 0 && dv0 > 0 && dv1 > 0) {
                 atomicAdd(&frame[v], 1);
                 sm.acc[ST_INTERIOR] += 1;
@@ -1299,6 +1308,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 int32_t x = v;
                 for (int32_t dxv = side ? dv1 : dv0; dxv > 1; --dxv) {  // x on level dxv
                     const uint32_t want = level_code(dxv - 1);
+                    const bool one = dxv - 1 <= 1;  // the candidates' sigma is 1
                     const int32_t rs = row_ptr[x], deg = row_ptr[x + 1] - rs;
                     // predecessors = x's neighbours on level dxv - 1 of this side
                     const int32_t llo = loffs[dxv - 1], lhi = loffs[dxv];
@@ -1331,7 +1341,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                                 const int at = atomicAdd(&sm.ncand, 1);
                                 if (at < STAGE) {
                                     sm.sv[at] = po;
-                                    sm.sw[at] = sg[p];
+                                    sm.sw[at] = one ? Sigma{1u, 0u} : sg[p];
                                 }
                             }
                         }
@@ -1353,7 +1363,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                         const bool mine = lane < deg;
                         const int32_t p = mine ? col[rs + lane] : 0;
                         const uint32_t cw = code[p >> 3];
-                        const Sigma sp = sg[p];
+                        const Sigma sp = one ? Sigma{1u, 0u} : sg[p];
                         const u128 part = (mine && ((cw >> code_shift(p, side)) & 3u) == want) ? to128(sp)
                                                                                                : (u128)0;
                         u128 tot;
@@ -1374,15 +1384,15 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                             const uint32_t c1 = (code[p1 >> 3] >> code_shift(p1, side)) & 3u;
                             const uint32_t c2 = (code[p2 >> 3] >> code_shift(p2, side)) & 3u;
                             const uint32_t c3 = (code[p3 >> 3] >> code_shift(p3, side)) & 3u;
-                            if (c0 == want) part += to128(sg[p0]);
-                            if (c1 == want) part += to128(sg[p1]);
-                            if (c2 == want) part += to128(sg[p2]);
-                            if (c3 == want) part += to128(sg[p3]);
+                            if (c0 == want) part += one ? (u128)1 : to128(sg[p0]);
+                            if (c1 == want) part += one ? (u128)1 : to128(sg[p1]);
+                            if (c2 == want) part += one ? (u128)1 : to128(sg[p2]);
+                            if (c3 == want) part += one ? (u128)1 : to128(sg[p3]);
                         }
                         for (; e < e1; ++e) {
                             const int32_t p = col[e];
                             if (((code[p >> 3] >> code_shift(p, side)) & 3u) == want)
-                                part += to128(sg[p]);
+                                part += one ? (u128)1 : to128(sg[p]);
                         }
                         u128 tot;
                         const u128 ex_pre = T::excl_scan_u128(part, &tot, redA);
@@ -1392,7 +1402,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                             for (int32_t q = e0; q < e1; ++q) {
                                 const int32_t p = col[q];
                                 if (((code[p >> 3] >> code_shift(p, side)) & 3u) != want) continue;
-                                acc += to128(sg[p]);
+                                acc += one ? (u128)1 : to128(sg[p]);
                                 if (acc > r) {
                                     sm.pick = p;
                                     break;
