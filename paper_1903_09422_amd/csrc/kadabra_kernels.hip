@@ -834,7 +834,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                         const int32_t e = r * PA * TEAM + lane;
                         int32_t ai[PA], yv[PA], pv[PA];
                         uint32_t wd[PA], old[PA];
-                        bool hit[PA];
+                        bool hit[PA], won[PA];
                         Sigma sp[PA];
 #pragma unroll
                         for (int k = 0; k < PA; ++k) {
@@ -863,11 +863,12 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
 #pragma unroll
                         for (int k = 0; k < PA; ++k) {
                             const bool claimed = hit[k] && ((old[k] >> code_shift(yv[k], X)) & 3u) == 0u;
+                            won[k] = claimed;
                             const int pp = wave_append(claimed, cnt_new);
                             if (claimed) {
                                 ballx[base_new + pp] = yv[k];
                                 if (pp < STAGE) sm.sv[pp] = yv[k];
-                                if (!implicit_new) sigx[yv[k]] = Sigma{0u, 0u};
+                                if (!implicit_new) sigx[yv[k]] = sp[k];  // the claim's own hit
                             }
                             const int q = wave_append(claimed, cnt_meet);
                             if (claimed) meet[q] = yv[k];
@@ -877,7 +878,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                         // sigma_X(y) += sigma_X(p)
 #pragma unroll
                         for (int k = 0; k < PA; ++k) {
-                            if (!hit[k]) continue;
+                            if (!hit[k] || won[k]) continue;
                             if (low_mass) {
                                 (void)wg_add_u64(&sigx[yv[k]].lo, sp[k].lo);
                             } else {
@@ -992,13 +993,15 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                                 if (lds_try) {
                                     if (p < HMAX) hash_insert(hkeys, HMASK, w);
                                 } else if (!implicit_new) {
-                                    sigx[w] = Sigma{0u, 0u};  // summed in global memory below
+                                    // summed in global memory: the claim's own arc is a
+                                    // store, the other arcs into w add after a barrier
+                                    sigx[w] = sm.cm[ow[k]];
                                 }
                             }
                             const bool is_meet = claimed && dyc[k] != 0u;
                             const int q = wave_append(is_meet, cnt_meet);
                             if (is_meet) meet[q] = w;
-                            add[k] = e + k * TEAM < tot && dxc[k] == code_new;
+                            add[k] = e + k * TEAM < tot && dxc[k] == code_new && (lds_try || !claimed);
                         }
                     };
                     // sigma(w) += sigma(owner) for every arc into the new level, in
@@ -1034,8 +1037,10 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     // rounds of ARCS * TEAM arcs, the same number in every lane.  A
                     // vertex's sigma is written only by the sample that reaches it
                     // (nothing clears it afterwards): in global memory the winner of
-                    // its claim zeroes it, and the adds of a round follow a barrier
-                    // after the round's claims.
+                    // its claim stores its own arc's count, and the other arcs into
+                    // the vertex add theirs after a barrier that follows the round's
+                    // claims (most new vertices have one predecessor: a store, no
+                    // atomic).
                     const int32_t rounds = (tot + ARCS * TEAM - 1) / (ARCS * TEAM);
                     for (int32_t r = 0; r < rounds; ++r) {
                         claim_round(r * ARCS * TEAM + lane, wv, ow, add);
