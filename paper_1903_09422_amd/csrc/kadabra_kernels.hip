@@ -129,6 +129,74 @@ __device__ __forceinline__ uint64_t ceil_shr256(U256 x, int sh)
 }
 
 // ---------------------------------------------------------------------------
+// Wavefront scans on the data-parallel primitives (DPP) of the vector ALU.
+// dmov<CTRL, ROWS>(x) is x moved across the lanes of a wavefront by a fixed
+// pattern; a lane with no source, or in a row (16 lanes) that ROWS leaves
+// out, receives 0.  wave_scan is an inclusive scan in lane order for an
+// associative op with identity 0 (a sum, an unsigned maximum): row_shr by 1,
+// 2, 4 and 8 scans each row, then the last lane of rows 0 and 2 is combined
+// into rows 1 and 3 (row_bcast:15) and the last lane of row 1 into rows 2
+// and 3 (row_bcast:31).  Every lane must be active.  last_lane reads lane 63
+// (the whole wavefront's result) into scalar registers.
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dmov(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dmov(uint64_t x)
+{
+    return (uint64_t)dmov<CTRL, ROWS>((uint32_t)x) | ((uint64_t)dmov<CTRL, ROWS>((uint32_t)(x >> 32)) << 32);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ u128 dmov(u128 x)
+{
+    return (u128)dmov<CTRL, ROWS>((uint64_t)x) | ((u128)dmov<CTRL, ROWS>((uint64_t)(x >> 64)) << 64);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ U256 dmov(U256 x)
+{
+    return U256{dmov<CTRL, ROWS>(x.hi), dmov<CTRL, ROWS>(x.lo)};
+}
+
+template <typename V, typename Op>
+__device__ __forceinline__ V wave_scan(V x, Op op)
+{
+    x = op(x, dmov<0x111, 0xf>(x));  // row_shr:1
+    x = op(x, dmov<0x112, 0xf>(x));  // row_shr:2
+    x = op(x, dmov<0x114, 0xf>(x));  // row_shr:4
+    x = op(x, dmov<0x118, 0xf>(x));  // row_shr:8
+    x = op(x, dmov<0x142, 0xa>(x));  // row_bcast:15 into rows 1 and 3
+    x = op(x, dmov<0x143, 0xc>(x));  // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
+__device__ __forceinline__ uint32_t last_lane(uint32_t x) { return (uint32_t)__builtin_amdgcn_readlane((int)x, 63); }
+__device__ __forceinline__ uint64_t last_lane(uint64_t x)
+{
+    return (uint64_t)last_lane((uint32_t)x) | ((uint64_t)last_lane((uint32_t)(x >> 32)) << 32);
+}
+__device__ __forceinline__ u128 last_lane(u128 x)
+{
+    return (u128)last_lane((uint64_t)x) | ((u128)last_lane((uint64_t)(x >> 64)) << 64);
+}
+__device__ __forceinline__ U256 last_lane(U256 x) { return U256{last_lane(x.hi), last_lane(x.lo)}; }
+
+struct OpAdd {
+    template <typename V>
+    __device__ __forceinline__ V operator()(V a, V b) const { return a + b; }
+};
+struct OpMax {
+    template <typename V>
+    __device__ __forceinline__ V operator()(V a, V b) const { return b > a ? b : a; }
+    __device__ __forceinline__ U256 operator()(U256 a, U256 b) const
+    {
+        return (b.hi > a.hi || (b.hi == a.hi && b.lo > a.lo)) ? b : a;
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Team primitives.  A team is the whole workgroup (TEAM == blockDim.x), one
 // wavefront (64) or four (256).  A sample's state is touched by its own
 // workgroup only, so workgroup scope is all the ordering it needs: sync() is
@@ -141,13 +209,6 @@ struct Team {
 
     __device__ static __forceinline__ void sync() { __syncthreads(); }
 
-    __device__ static __forceinline__ uint64_t wave_sum(uint64_t v)
-    {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        return v;
-    }
-
     // Team reductions: result in every lane.  A reduction has one barrier,
     // before it reads the per-wavefront words in red; it does not wait for
     // those reads to finish, so consecutive reductions must use different red
@@ -157,7 +218,7 @@ struct Team {
     // sum over the team
     __device__ static uint64_t sum_u64(uint64_t v, uint64_t *red)
     {
-        v = wave_sum(v);
+        v = last_lane(wave_scan(v, OpAdd{}));
         if (WAVES == 1) return v;
         const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) red[w] = v;
@@ -170,12 +231,7 @@ struct Team {
 
     __device__ static u128 sum_u128(u128 v, uint64_t *red)
     {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const uint64_t lo = __shfl_xor((uint64_t)v, o, 64);
-            const uint64_t hi = __shfl_xor((uint64_t)(v >> 64), o, 64);
-            v += ((u128)hi << 64) | lo;
-        }
+        v = last_lane(wave_scan(v, OpAdd{}));
         if (WAVES == 1) return v;
         const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
@@ -192,25 +248,18 @@ struct Team {
     // sums a 64-bit and a 128-bit value over the team with one exchange
     __device__ static void sum_u64_u128(uint64_t *a, u128 *b, uint64_t *red)
     {
-        uint64_t x = *a, lo = (uint64_t)*b, hi = (uint64_t)(*b >> 64);
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            x += __shfl_xor(x, o, 64);
-            const uint64_t l2 = __shfl_xor(lo, o, 64), h2 = __shfl_xor(hi, o, 64);
-            const uint64_t l = lo + l2;
-            hi = hi + h2 + (l < lo ? 1u : 0u);
-            lo = l;
-        }
+        const uint64_t x = last_lane(wave_scan(*a, OpAdd{}));
+        const u128 y = last_lane(wave_scan(*b, OpAdd{}));
         if (WAVES == 1) {
             *a = x;
-            *b = ((u128)hi << 64) | lo;
+            *b = y;
             return;
         }
         const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
             red[3 * w] = x;
-            red[3 * w + 1] = lo;
-            red[3 * w + 2] = hi;
+            red[3 * w + 1] = (uint64_t)y;
+            red[3 * w + 2] = (uint64_t)(y >> 64);
         }
         __syncthreads();
         uint64_t tx = 0;
@@ -226,13 +275,7 @@ struct Team {
 
     __device__ static u128 max_u128(u128 v, uint64_t *red)
     {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const uint64_t lo = __shfl_xor((uint64_t)v, o, 64);
-            const uint64_t hi = __shfl_xor((uint64_t)(v >> 64), o, 64);
-            const u128 x = ((u128)hi << 64) | lo;
-            v = x > v ? x : v;
-        }
+        v = last_lane(wave_scan(v, OpMax{}));
         if (WAVES == 1) return v;
         const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
@@ -251,15 +294,7 @@ struct Team {
 
     __device__ static U256 max_u256(U256 v, uint64_t *red)
     {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            U256 x;
-            x.lo = ((u128)__shfl_xor((uint64_t)(v.lo >> 64), o, 64) << 64) |
-                   __shfl_xor((uint64_t)v.lo, o, 64);
-            x.hi = ((u128)__shfl_xor((uint64_t)(v.hi >> 64), o, 64) << 64) |
-                   __shfl_xor((uint64_t)v.hi, o, 64);
-            if (x.hi > v.hi || (x.hi == v.hi && x.lo > v.lo)) v = x;
-        }
+        v = last_lane(wave_scan(v, OpMax{}));
         if (WAVES == 1) return v;
         const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
@@ -284,14 +319,9 @@ struct Team {
     __device__ static int32_t excl_scan_i32(int32_t v, int32_t *total, uint64_t *red)
     {
         const int lw = threadIdx.x & 63;
-        int32_t x = v;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int32_t y = __shfl_up(x, o, 64);
-            if (lw >= o) x += y;
-        }
+        const int32_t x = (int32_t)wave_scan((uint32_t)v, OpAdd{});
         if (WAVES == 1) {
-            *total = __shfl(x, 63, 64);
+            *total = (int32_t)last_lane((uint32_t)x);
             return x - v;
         }
         const int w = threadIdx.x >> 6;
@@ -312,15 +342,9 @@ struct Team {
     __device__ static u128 excl_scan_u128(u128 v, u128 *total, uint64_t *red)
     {
         const int lw = threadIdx.x & 63;
-        u128 x = v;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint64_t lo = __shfl_up((uint64_t)x, o, 64);
-            const uint64_t hi = __shfl_up((uint64_t)(x >> 64), o, 64);
-            if (lw >= o) x += ((u128)hi << 64) | lo;
-        }
+        const u128 x = wave_scan(v, OpAdd{});
         if (WAVES == 1) {
-            *total = ((u128)__shfl((uint64_t)(x >> 64), 63, 64) << 64) | __shfl((uint64_t)x, 63, 64);
+            *total = last_lane(x);
             return x - v;
         }
         const int w = threadIdx.x >> 6;
@@ -358,12 +382,14 @@ __device__ __forceinline__ int wave_append(bool take, int32_t *cnt)
     const uint64_t act = __ballot(take);
     if (act == 0) return -1;
     const int lw = threadIdx.x & 63;
-    const int leader = __ffsll((unsigned long long)act) - 1;
+    const int leader = __ffsll((unsigned long long)act) - 1;  // uniform
     int base = 0;
     if (lw == leader) base = atomicAdd(cnt, __popcll(act));
-    base = __shfl(base, leader, 64);
-    const uint64_t below = lw ? (act & ((~0ull) >> (64 - lw))) : 0ull;
-    return take ? base + __popcll(below) : -1;
+    base = __builtin_amdgcn_readlane(base, leader);
+    // lanes of act below this one
+    const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+    return take ? base + below : -1;
 }
 
 // Optional per-phase cycle counters (compile with -DKADABRA_PHASE_TIMERS):
@@ -1262,11 +1288,8 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 tot = T::sum_u64(tot, redB);
                 // team min / max of the ids (as maxima of n - id and id + 1)
                 uint64_t mn = (uint64_t)(uint32_t)(nv - vmin), mx = (uint64_t)(uint32_t)(vmax + 1);
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    mn = max(mn, (uint64_t)__shfl_xor(mn, o, 64));
-                    mx = max(mx, (uint64_t)__shfl_xor(mx, o, 64));
-                }
+                mn = last_lane(wave_scan(mn, OpMax{}));
+                mx = last_lane(wave_scan(mx, OpMax{}));
                 if (T::WAVES > 1) {
                     uint64_t *const rr = redA;  // then a sync
                     const int wv = lane >> 6;
