@@ -966,25 +966,25 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     // owners, column entries, code words, claims and appends.  wv,
                     // ow and add receive the arcs and which of them enter the new level.
                     auto claim_round = [&](int32_t e, int32_t (&wv)[ARCS], int32_t (&ow)[ARCS], bool (&add)[ARCS]) {
-                        // owners and arc positions (LDS only); an arc past the end
-                        // reads arc 0 of the graph, so that every load below is
+                        // owners and arc positions (LDS only), each arc's column
+                        // entry requested as soon as its position is known, so that
+                        // the loads overlap the next owners' searches; an arc past
+                        // the end reads arc 0 of the graph, so that every load is
                         // unconditional (the round loop is the same for every lane,
                         // so in the last round even a lane's first arc may be past it)
-                        int32_t ai[ARCS];
                         uint32_t wd[ARCS];
     #pragma unroll
                         for (int k = 0; k < ARCS; ++k) {
                             const int32_t ek = e + k * TEAM;
+                            int32_t ai = 0;
                             if (ek < tot) {
                                 ow[k] = owner_of(ek);
-                                ai[k] = sm.crs[ow[k]] + (ek - sm.cpfx[ow[k]]);
+                                ai = sm.crs[ow[k]] + (ek - sm.cpfx[ow[k]]);
                             } else {
                                 ow[k] = own;
-                                ai[k] = 0;
                             }
+                            wv[k] = col[ai];
                         }
-    #pragma unroll
-                        for (int k = 0; k < ARCS; ++k) wv[k] = col[ai[k]];
     #pragma unroll
                         for (int k = 0; k < ARCS; ++k) wd[k] = code[wv[k] >> 3];
                         // claims: decided from the words read, and all issued before
