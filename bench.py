@@ -146,7 +146,9 @@ def main() -> int:
     ap.add_argument("--no-rmat22", action="store_true",
                     help="serve: leave R-MAT scale 22 out of the graph pool")
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--team", type=int, default=0)
+    ap.add_argument("--team", type=int, default=0,
+                    help="lanes per sample; 0: the workload's mapping (WORKLOAD_TEAM, else the "
+                         "library's automatic choice)")
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--frames", type=int, default=1)
     ap.add_argument("--overlap", type=int, default=1)
@@ -225,6 +227,15 @@ def _leg_summary(leg: dict) -> dict:
     return {k: leg[k] for k in keep if k in leg}
 
 
+# Mapping per single-query workload (no result depends on it): 128-lane teams,
+# eight per CU, were measured faster than the library's automatic choice
+# (256-lane teams, four per CU) on R-MAT-18 (+3 to +7%) and ER-4096 (+5%), and
+# level on the grid.  The library keeps 256 lanes by default because 128-lane
+# teams double the slot pool, and a process that holds many graph handles (the
+# 64-graph batch leg) then runs out of device memory.
+WORKLOAD_TEAM = {"rmat18": 128, "er4096": 128}
+
+
 def measure_single(workload, args, steps, warmup, balanced_steps, with_cpu, copy_gbs) -> dict:
     """One query of a named workload, run `steps` times (one step = one
     complete adaptive run plus the device scores)."""
@@ -235,7 +246,7 @@ def measure_single(workload, args, steps, warmup, balanced_steps, with_cpu, copy
     g, eps, delta, n_check = graphs.workload(workload)
     dev = Graph.from_csr(g)  # uploads the CSR: inputs resident before timing
     dev.set_param("check_interval", n_check)
-    dev.set_param("team", args.team)
+    dev.set_param("team", args.team if args.team else WORKLOAD_TEAM.get(workload, 0))
     dev.set_param("slots", args.slots)
     dev.set_param("frames", args.frames)
     dev.set_param("overlap", args.overlap)

@@ -214,7 +214,7 @@ def test_mapping_does_not_change_results():
                    {"epochs_per_launch": 4, "overlap": 0},
                    {"frames": 8}, {"overlap": 0}, {"team": 64, "frames": 3, "overlap": 0},
                    {"probe_min": 0}, {"probe_min": 1 << 40}, {"team": 64, "probe_min": 0},
-                   {"probe_pull": 1}, {"probe_pull": 1, "probe_min": 0}):
+                   {"team": 256, "probe_pull": 1}, {"team": 256, "probe_pull": 1, "probe_min": 0}, {}):
         print("  mapping", params, flush=True)
         got = gpu_run(g, eps, delta, ref["seed"], n_check, **params)
         assert got.tau == base.tau and np.array_equal(got.counts, base.counts), params
