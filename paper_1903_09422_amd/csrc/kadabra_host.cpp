@@ -1774,6 +1774,47 @@ std::vector<int32_t> rcm_order(int32_t n, const int32_t *rp, const int32_t *col)
     return order;
 }
 
+// Locality order for high-diameter graphs: clusters of 256 vertices (one
+// line of code words) grown by BFS over unplaced vertices from seeds taken in
+// reverse Cuthill-McKee order, so that consecutive clusters lie near each
+// other; inside each cluster, sub-clusters of 8 (one 128-byte line of sigma)
+// grown the same way from the cluster's vertices in their BFS order.  A
+// sample's BFS ball then covers few lines of either.  Returns order[k] = the
+// original id of internal vertex k.
+std::vector<int32_t> cluster_order(int32_t n, const int32_t *rp, const int32_t *col)
+{
+    const std::vector<int32_t> seeds = rcm_order(n, rp, col);
+    std::vector<uint8_t> mark((size_t)n, 0);  // 0 unplaced, 1 in the current cluster, 2 placed
+    std::vector<int32_t> order, cl, sub;
+    order.reserve((size_t)n);
+    // BFS from seed over vertices marked `from`, marking them `to`, at most cap of them
+    auto grow = [&](int32_t seed, size_t cap, uint8_t from, uint8_t to, std::vector<int32_t> &out) {
+        out.clear();
+        out.push_back(seed);
+        mark[(size_t)seed] = to;
+        for (size_t h = 0; h < out.size() && out.size() < cap; ++h) {
+            const int32_t u = out[h];
+            for (int32_t e = rp[u]; e < rp[u + 1] && out.size() < cap; ++e) {
+                const int32_t w = col[e];
+                if (mark[(size_t)w] == from) {
+                    mark[(size_t)w] = to;
+                    out.push_back(w);
+                }
+            }
+        }
+    };
+    for (int32_t sd : seeds) {
+        if (mark[(size_t)sd] != 0) continue;
+        grow(sd, 256, 0, 1, cl);
+        for (int32_t v : cl) {
+            if (mark[(size_t)v] != 1) continue;
+            grow(v, 8, 1, 2, sub);
+            order.insert(order.end(), sub.begin(), sub.end());
+        }
+    }
+    return order;
+}
+
 // Replaces the device graph by its internal order (a layout change only:
 // every result is the one of the original order, see GraphData).  BFS balls
 // of a high-diameter graph then fall in fewer cache lines.
@@ -1781,7 +1822,7 @@ int relabel_for_locality(GraphData &gd, const int32_t *row_ptr, const int32_t *c
 {
     const int32_t n = gd.n;
     const size_t m = (size_t)gd.arcs;
-    std::vector<int32_t> iperm = rcm_order(n, row_ptr, col);
+    std::vector<int32_t> iperm = cluster_order(n, row_ptr, col);
     std::vector<int32_t> perm((size_t)n);
     for (int32_t k = 0; k < n; ++k) perm[(size_t)iperm[(size_t)k]] = k;
     std::vector<int32_t> rp2((size_t)n + 1), col2(m), colo(m);

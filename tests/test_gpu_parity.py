@@ -124,8 +124,9 @@ def _broom(handle, leaves):
 
 @pytest.mark.parametrize("team", [64, 256])
 def test_relabelled_graphs(team):
-    """High-diameter graphs run in an internal vertex order (reverse
-    Cuthill-McKee) with every tie still broken by original id: the results
+    """High-diameter graphs run in an internal vertex order (BFS-grown
+    clusters seeded in reverse Cuthill-McKee order) with every tie still
+    broken by original id: the results
     equal the oracle's.  Meeting sets larger than a 64-lane team (grid), and
     backtracking through a hub by the level-list search (broom)."""
     cases = [(G.cycle_graph(300), 0.05, 128), (G.path_graph(200), 0.05, 100),
