@@ -90,9 +90,9 @@ typedef struct {
  *            [0, n), no self-loops, and (u, v) present iff (v, u) present
  *   out      receives the handle (NULL on failure)
  * A graph whose vertex-diameter bound is 64 or more is stored on the device in
- * a cluster order (computed on the host: BFS-grown clusters of 256 vertices,
+ * a cluster order (computed on the host: BFS-grown clusters of 128 vertices,
  * seeded in reverse Cuthill-McKee order, each split into BFS-grown clusters of
- * 8), which keeps the search balls of high-diameter graphs compact in memory;
+ * 32), which keeps the search balls of high-diameter graphs compact in memory;
  * every result and every output is still in, and tie-broken by, the given
  * vertex ids.
  * The caller keeps ownership of its arrays.  Errors: EINVAL (malformed CSR),

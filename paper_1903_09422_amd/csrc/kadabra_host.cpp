@@ -1774,13 +1774,14 @@ std::vector<int32_t> rcm_order(int32_t n, const int32_t *rp, const int32_t *col)
     return order;
 }
 
-// Locality order for high-diameter graphs: clusters of 256 vertices (one
-// line of code words) grown by BFS over unplaced vertices from seeds taken in
-// reverse Cuthill-McKee order, so that consecutive clusters lie near each
-// other; inside each cluster, sub-clusters of 8 (one 128-byte line of sigma)
+// Locality order for high-diameter graphs: clusters of 128 vertices (half a
+// 128-byte line of code words) grown by BFS over unplaced vertices from seeds
+// taken in reverse Cuthill-McKee order, so that consecutive clusters lie near
+// each other; inside each cluster, sub-clusters of 32 (four lines of sigma)
 // grown the same way from the cluster's vertices in their BFS order.  A
-// sample's BFS ball then covers few lines of either.  Returns order[k] = the
-// original id of internal vertex k.
+// sample's BFS ball then covers few lines of either.  (Sizes measured on the
+// 1024^2 grid: 128 and 32 beat 256 and 8 by 2.6%, and 512 or more outer
+// vertices lose.)  Returns order[k] = the original id of internal vertex k.
 std::vector<int32_t> cluster_order(int32_t n, const int32_t *rp, const int32_t *col)
 {
     const std::vector<int32_t> seeds = rcm_order(n, rp, col);
@@ -1805,10 +1806,10 @@ std::vector<int32_t> cluster_order(int32_t n, const int32_t *rp, const int32_t *
     };
     for (int32_t sd : seeds) {
         if (mark[(size_t)sd] != 0) continue;
-        grow(sd, 256, 0, 1, cl);
+        grow(sd, 128, 0, 1, cl);
         for (int32_t v : cl) {
             if (mark[(size_t)v] != 1) continue;
-            grow(v, 8, 1, 2, sub);
+            grow(v, 32, 1, 2, sub);
             order.insert(order.end(), sub.begin(), sub.end());
         }
     }
