@@ -152,7 +152,9 @@ typedef struct {
  *   "probe_min"       k >= 0: expansions scanning at least k arcs first look
  *                     for the meeting set without materialising the new level;
  *                     -1 (default): when the product of the two frontiers'
- *                     degree sums reaches four times the arc count.
+ *                     degree sums reaches the arc count (four times the arc
+ *                     count on graphs whose vertex-diameter bound is 64 or
+ *                     more).
  *   "probe_pull"      1: a meeting probe scans the rows of the other side's
  *                     frontier for neighbours on the expanding side's
  *                     frontier (pull form) instead of the expanding side's

@@ -277,6 +277,13 @@ int get_common_param(const Params &p, const char *key, int64_t *value)
     return 0;
 }
 
+// Graphs whose vertex-diameter bound reaches this are high-diameter: they are
+// relabelled for locality, and the sampler's automatic meeting probe asks for
+// four expected hits instead of one (QueryDesc::probe_hits).
+constexpr int32_t kRelabelMinVd = 64;
+
+int32_t probe_hits_for(int32_t vd) { return vd >= kRelabelMinVd ? 4 : 1; }
+
 // A graph resident on the device, plus what depends on the graph only.
 // On a high-diameter graph the device arrays use an internal vertex order
 // (relabel_for_locality); d_perm maps original to internal ids, d_iperm back,
@@ -887,6 +894,7 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
                 d.epoch_len = 1;
                 d.claim_begin = total;
                 d.probe_min = q.probe_min;
+                d.probe_hits = probe_hits_for(q.gd->vd);
                 d.num_arcs = q.gd->arcs;
                 d.n = q.gd->n;
                 d.nframes = 1;
@@ -927,6 +935,7 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
             d.epoch_len = q.N;
             d.claim_begin = total;
             d.probe_min = q.probe_min;
+            d.probe_hits = probe_hits_for(q.gd->vd);
             d.num_arcs = q.gd->arcs;
             d.n = q.gd->n;
             d.nframes = q.nframes;
@@ -1713,8 +1722,6 @@ StaticLayout static_layout(int64_t n, int32_t lcap, int64_t slots)
 
 namespace {
 
-// Graphs whose vertex-diameter bound reaches this are relabelled for locality.
-constexpr int32_t kRelabelMinVd = 64;
 
 // Reverse Cuthill-McKee order: per component (in order of its smallest id), a
 // BFS from a pseudo-peripheral vertex (of the deepest level of a BFS from the
@@ -2227,6 +2234,7 @@ int kadabra_run_static(kadabra_graph *g, double eps, double delta, uint64_t seed
         d.epoch_len = N;
         d.claim_begin = 0;
         d.probe_min = p.probe_min;
+        d.probe_hits = probe_hits_for(gd.vd);
         d.num_arcs = gd.arcs;
         d.n = gd.n;
         d.nframes = 1;

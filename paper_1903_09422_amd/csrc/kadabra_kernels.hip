@@ -664,7 +664,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
         const gint32_t *const comp = as_global(qd->comp);
         const int32_t nv = qd->n;
         const uint64_t seed = qd->seed;
-        const int64_t probe_min = qd->probe_min, num_arcs = qd->num_arcs;
+        const int64_t probe_min = qd->probe_min, num_arcs = qd->num_arcs, probe_hits = qd->probe_hits;
         int32_t *const frame =
             qd->frames + ((size_t)qpar * qd->nframes + (size_t)(blockIdx.x % qd->nframes)) * (size_t)nv;
         if (qctl != acc_ctl || qstat != acc_par) {
@@ -764,12 +764,15 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
             // otherwise the level is expanded in full.  The probe cannot skip a
             // rescaling: it runs only when the frontier's mass is below 2^104.
             // Auto rule (probe_min < 0): probe when the arcs leaving X's
-            // frontier are expected to hit Y's frontier at least four times,
-            // D_X D_Y >= 4 x (number of arcs), an arc landing on a vertex with
-            // probability proportional to its degree.
+            // frontier are expected to hit Y's frontier at least probe_hits
+            // times, D_X D_Y >= probe_hits x (number of arcs), an arc landing
+            // on a vertex with probability proportional to its degree.  The
+            // host sets 1 on low-diameter graphs and 4 on high-diameter ones,
+            // whose arcs stay local: there the estimate counts hits long
+            // before the balls touch, and a failed probe costs a rescan.
             const int64_t dsy = X ? dsum0 : dsum1;
             const bool want_probe = (probe_min >= 0) ? (dsx >= probe_min)
-                                                     : (dsx * dsy >= 4 * num_arcs);
+                                                     : (dsx * dsy >= probe_hits * num_arcs);
             const bool probe = !retry && want_probe && bitw128(X ? fmass1 : fmass0) <= SIGMA_BITS;
             if (lane == 0 && !retry) {
                 sm.acc[ST_VEXP] += (uint64_t)(fhix - flox);
