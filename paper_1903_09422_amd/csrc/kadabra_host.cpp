@@ -278,11 +278,12 @@ int get_common_param(const Params &p, const char *key, int64_t *value)
 }
 
 // Graphs whose vertex-diameter bound reaches this are high-diameter: they are
-// relabelled for locality, and the sampler's automatic meeting probe asks for
-// four expected hits instead of one (QueryDesc::probe_hits).
+// relabelled for locality, the sampler's automatic meeting probe asks for
+// more expected hits (QueryDesc::probe_h8, in eighths of a hit), and a probe
+// that meets nothing in its first round is given up (QueryDesc::probe_quit).
 constexpr int32_t kRelabelMinVd = 64;
 
-int32_t probe_hits_for(int32_t vd) { return vd >= kRelabelMinVd ? 4 : 1; }
+int32_t probe_h8_for(int32_t vd) { return vd >= kRelabelMinVd ? 32 : 8; }
 
 // A graph resident on the device, plus what depends on the graph only.
 // On a high-diameter graph the device arrays use an internal vertex order
@@ -894,7 +895,8 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
                 d.epoch_len = 1;
                 d.claim_begin = total;
                 d.probe_min = q.probe_min;
-                d.probe_hits = probe_hits_for(q.gd->vd);
+                d.probe_h8 = probe_h8_for(q.gd->vd);
+                d.probe_quit = q.gd->vd >= kRelabelMinVd ? 1 : 0;
                 d.num_arcs = q.gd->arcs;
                 d.n = q.gd->n;
                 d.nframes = 1;
@@ -935,7 +937,8 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
             d.epoch_len = q.N;
             d.claim_begin = total;
             d.probe_min = q.probe_min;
-            d.probe_hits = probe_hits_for(q.gd->vd);
+            d.probe_h8 = probe_h8_for(q.gd->vd);
+            d.probe_quit = q.gd->vd >= kRelabelMinVd ? 1 : 0;
             d.num_arcs = q.gd->arcs;
             d.n = q.gd->n;
             d.nframes = q.nframes;
@@ -2234,7 +2237,8 @@ int kadabra_run_static(kadabra_graph *g, double eps, double delta, uint64_t seed
         d.epoch_len = N;
         d.claim_begin = 0;
         d.probe_min = p.probe_min;
-        d.probe_hits = probe_hits_for(gd.vd);
+        d.probe_h8 = probe_h8_for(gd.vd);
+        d.probe_quit = gd.vd >= kRelabelMinVd ? 1 : 0;
         d.num_arcs = gd.arcs;
         d.n = gd.n;
         d.nframes = 1;

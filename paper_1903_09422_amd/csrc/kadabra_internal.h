@@ -89,8 +89,10 @@ struct QueryDesc {
     int32_t gate;         // -1, or the set of the boundary before lo: if its check found no
                           // violation the run has stopped and this launch does no work for it
     int32_t stat_set;     // -1: work counters by epoch set; else this set (first phase)
-    int32_t probe_hits;   // auto probe rule (probe_min < 0): probe when the frontiers' degree
-                          // sums D_X D_Y reach probe_hits x num_arcs
+    int32_t probe_h8;     // auto probe rule (probe_min < 0): probe when the frontiers' degree
+                          // sums D_X D_Y reach probe_h8 / 8 x num_arcs
+    int32_t probe_quit;   // 1: a probe whose first round meets nothing is given up
+    int32_t pad;
     // A first phase is a descriptor with lo = INT64_MIN (its samples' indices
     // are then kFirstPhaseBase + m as unsigned), nsets = nframes = 1,
     // frames = c1 and stat_set = kFirstSet.

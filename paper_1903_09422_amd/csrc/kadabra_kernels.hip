@@ -664,7 +664,8 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
         const gint32_t *const comp = as_global(qd->comp);
         const int32_t nv = qd->n;
         const uint64_t seed = qd->seed;
-        const int64_t probe_min = qd->probe_min, num_arcs = qd->num_arcs, probe_hits = qd->probe_hits;
+        const int64_t probe_min = qd->probe_min, num_arcs = qd->num_arcs, probe_h8 = qd->probe_h8;
+        const bool probe_quit = qd->probe_quit != 0;
         int32_t *const frame =
             qd->frames + ((size_t)qpar * qd->nframes + (size_t)(blockIdx.x % qd->nframes)) * (size_t)nv;
         if (qctl != acc_ctl || qstat != acc_par) {
@@ -764,15 +765,15 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
             // otherwise the level is expanded in full.  The probe cannot skip a
             // rescaling: it runs only when the frontier's mass is below 2^104.
             // Auto rule (probe_min < 0): probe when the arcs leaving X's
-            // frontier are expected to hit Y's frontier at least probe_hits
-            // times, D_X D_Y >= probe_hits x (number of arcs), an arc landing
-            // on a vertex with probability proportional to its degree.  The
-            // host sets 1 on low-diameter graphs and 4 on high-diameter ones,
-            // whose arcs stay local: there the estimate counts hits long
-            // before the balls touch, and a failed probe costs a rescan.
+            // frontier are expected to hit Y's frontier at least h =
+            // probe_h8 / 8 times, D_X D_Y >= h x (number of arcs), an arc
+            // landing on a vertex with probability proportional to its
+            // degree.  The host sets a small h on low-diameter graphs and a
+            // larger one on high-diameter graphs, whose arcs stay local: there
+            // the estimate counts hits long before the balls touch.
             const int64_t dsy = X ? dsum0 : dsum1;
             const bool want_probe = (probe_min >= 0) ? (dsx >= probe_min)
-                                                     : (dsx * dsy >= probe_hits * num_arcs);
+                                                     : (dsx * dsy >= probe_h8 * num_arcs / 8);
             const bool probe = !retry && want_probe && bitw128(X ? fmass1 : fmass0) <= SIGMA_BITS;
             if (lane == 0 && !retry) {
                 sm.acc[ST_VEXP] += (uint64_t)(fhix - flox);
@@ -920,6 +921,10 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     __syncthreads();
                 }
             } else {
+                bool gave_up = false;  // a probe given up after its first round
+                // (high-diameter graphs are the relabelled ones: a launch without
+                // one has no probe to give up, and the test is compiled out)
+                const bool quit_first = MAPPED && probe_quit && probe && dsx > (int64_t)ARCS * TEAM;
                 for (int32_t c0 = flox; c0 < fhix; c0 += TEAM) {
                     const int32_t idx = c0 + lane;
                     int32_t dg = 0;
@@ -1077,6 +1082,21 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                             __syncthreads();
                             global_adds(wv, ow, add);
                         }
+                        // On high-diameter graphs (probe_quit) a probe whose first
+                        // round meets no vertex of the other side, with more of
+                        // the level to scan, is given up: the level is then
+                        // expanded in full (as after a probe that met nothing).
+                        // There probes mostly fail; on low-diameter graphs a
+                        // probe's meeting vertices often come in later rounds.
+                        // The count is read after the round's barrier, so every
+                        // wave decides alike.
+                        if (quit_first && r == 0 && c0 == flox) {
+                            if (implicit_new) __syncthreads();  // else taken above
+                            if (uniform_i32(*cnt_meet) == 0) {
+                                gave_up = true;
+                                break;
+                            }
+                        }
                     }
                     if (lds_try) {
                         __syncthreads();  // the claims are done and the set is filled
@@ -1100,6 +1120,7 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                         }
                     }
                     __syncthreads();
+                    if (gave_up) break;
                 }
             }
             PHASE_MARK(1);
