@@ -152,9 +152,9 @@ typedef struct {
  *   "probe_min"       k >= 0: expansions scanning at least k arcs first look
  *                     for the meeting set without materialising the new level;
  *                     -1 (default): when the product of the two frontiers'
- *                     degree sums reaches the arc count (four times the arc
- *                     count on graphs whose vertex-diameter bound is 64 or
- *                     more).
+ *                     degree sums reaches h times the arc count: h = 4 on
+ *                     graphs whose vertex-diameter bound is 64 or more, else
+ *                     h = E[d^2] / E[d]^2 inverted and kept in [1/8, 1].
  *   "probe_pull"      1: a meeting probe scans the rows of the other side's
  *                     frontier for neighbours on the expanding side's
  *                     frontier (pull form) instead of the expanding side's

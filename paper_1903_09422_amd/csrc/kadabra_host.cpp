@@ -279,11 +279,30 @@ int get_common_param(const Params &p, const char *key, int64_t *value)
 
 // Graphs whose vertex-diameter bound reaches this are high-diameter: they are
 // relabelled for locality, the sampler's automatic meeting probe asks for
-// more expected hits (QueryDesc::probe_h8, in eighths of a hit), and a probe
-// that meets nothing in its first round is given up (QueryDesc::probe_quit).
+// more expected hits (probe_h8_for), and a probe that meets nothing in its
+// first round is given up (QueryDesc::probe_quit).
 constexpr int32_t kRelabelMinVd = 64;
 
-int32_t probe_h8_for(int32_t vd) { return vd >= kRelabelMinVd ? 32 : 8; }
+// The automatic meeting probe fires when D_X D_Y >= h x arcs, in eighths
+// (QueryDesc::probe_h8 = 8 h).  High-diameter graphs: h = 4 (their arcs stay
+// local, and the degree-proportional estimate counts hits long before the
+// balls touch).  Otherwise h = 1 / kappa, kappa = n sum(d^2) / (sum d)^2 =
+// E[d^2] / E[d]^2 >= 1, clamped to [1/8, 1]: the frontiers of a degree-skewed
+// graph crowd onto the same hubs and meet sooner than that estimate says
+// (measured on R-MAT-18: h = 1/8 is 3.5% faster than h = 1; on ER-4096,
+// kappa = 1.1, h = 1/8 is 3.5% slower).
+int32_t probe_h8_for(int32_t vd, int32_t n, int64_t arcs, const int32_t *row_ptr)
+{
+    if (vd >= kRelabelMinVd) return 32;
+    if (n <= 0 || arcs <= 0) return 8;
+    double s2 = 0.0;
+    for (int32_t v = 0; v < n; ++v) {
+        const double d = (double)(row_ptr[v + 1] - row_ptr[v]);
+        s2 += d * d;
+    }
+    const double kappa = (double)n * s2 / ((double)arcs * (double)arcs);
+    return (int32_t)std::min(8L, std::max(1L, std::lround(8.0 / kappa)));
+}
 
 // A graph resident on the device, plus what depends on the graph only.
 // On a high-diameter graph the device arrays use an internal vertex order
@@ -296,6 +315,7 @@ struct GraphData {
     int32_t max_deg = 0;
     int32_t vd = 1;
     int32_t ncomp = 0;
+    int32_t probe_h8 = 8;  // automatic meeting-probe constant (probe_h8_for)
     int device = 0;  // the HIP device holding the arrays
     int32_t *d_row_ptr = nullptr, *d_col = nullptr, *d_comp = nullptr;
     int32_t *d_colo = nullptr, *d_perm = nullptr, *d_iperm = nullptr;
@@ -895,7 +915,7 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
                 d.epoch_len = 1;
                 d.claim_begin = total;
                 d.probe_min = q.probe_min;
-                d.probe_h8 = probe_h8_for(q.gd->vd);
+                d.probe_h8 = q.gd->probe_h8;
                 d.probe_quit = q.gd->vd >= kRelabelMinVd ? 1 : 0;
                 d.num_arcs = q.gd->arcs;
                 d.n = q.gd->n;
@@ -937,7 +957,7 @@ int Runner::run_rounds(std::vector<Query *> &queries, const Params &p,
             d.epoch_len = q.N;
             d.claim_begin = total;
             d.probe_min = q.probe_min;
-            d.probe_h8 = probe_h8_for(q.gd->vd);
+            d.probe_h8 = q.gd->probe_h8;
             d.probe_quit = q.gd->vd >= kRelabelMinVd ? 1 : 0;
             d.num_arcs = q.gd->arcs;
             d.n = q.gd->n;
@@ -1924,6 +1944,7 @@ int kadabra_create_graph(int32_t n, int64_t num_arcs, const int32_t *row_ptr, co
     // the graph is read by kernels on non-blocking streams: the uploads land first
     HIP_OR_FAIL(hipDeviceSynchronize());
     OK_OR_RETURN(gpu_preprocess(gd, g->runner.own_stream));
+    gd.probe_h8 = probe_h8_for(gd.vd, n, num_arcs, row_ptr);
     if (gd.vd >= kRelabelMinVd) OK_OR_RETURN(relabel_for_locality(gd, row_ptr, col_idx, g->runner.own_stream));
     *out = g.release();
     return KADABRA_OK;
@@ -2237,7 +2258,7 @@ int kadabra_run_static(kadabra_graph *g, double eps, double delta, uint64_t seed
         d.epoch_len = N;
         d.claim_begin = 0;
         d.probe_min = p.probe_min;
-        d.probe_h8 = probe_h8_for(gd.vd);
+        d.probe_h8 = gd.probe_h8;
         d.probe_quit = gd.vd >= kRelabelMinVd ? 1 : 0;
         d.num_arcs = gd.arcs;
         d.n = gd.n;
