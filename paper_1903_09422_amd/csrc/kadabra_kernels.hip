@@ -503,10 +503,22 @@ __device__ __forceinline__ int32_t hash_slot(int32_t w, int32_t mask)
 {
     return (int32_t)(((uint32_t)w * 0x9E3779B1u) >> 16) & mask;
 }
-__device__ __forceinline__ void hash_insert(int32_t *keys, int32_t mask, int32_t w)
+__device__ __forceinline__ int32_t hash_insert(int32_t *keys, int32_t mask, int32_t w)
 {
     int32_t h = hash_slot(w, mask);
     while (atomicCAS(&keys[h], -1, w) != -1) h = (h + 1) & mask;
+    return h;
+}
+// w's slot, or -1 if w is not in the set
+__device__ __forceinline__ int32_t hash_find_opt(const int32_t *keys, int32_t mask, int32_t w)
+{
+    int32_t h = hash_slot(w, mask);
+    for (;;) {
+        const int32_t k = keys[h];
+        if (k == w) return h;
+        if (k == -1) return -1;
+        h = (h + 1) & mask;
+    }
 }
 __device__ __forceinline__ int32_t hash_find(const int32_t *keys, int32_t mask, int32_t w)
 {
@@ -784,24 +796,24 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
             int32_t *const cnt_new = &sm.nnext[lp];
             int32_t *const cnt_meet = &sm.nmeet[lp];
             const bool fcx = X ? fc1 : fc0;  // then the frontier is one chunk
-            // Small full levels may add sigma in LDS: the frontier is one chunk
-            // and its arcs one round per lane.  A claim's winner enters its
-            // vertex into an LDS hash set whose slot indexes an LDS count (the
-            // keys take side X's frontier cache, unused until this level's
-            // bookkeeping rewrites it).  After a barrier, if the new level has
-            // at most HMAX vertices, every arc into it adds there and each new
-            // vertex's count is stored once: no sigma atomics and no read-back
-            // in the level's chain of global accesses.  Otherwise the arcs kept
-            // in registers add into global memory as usual.  Not on probe levels
-            // (a retry reads the cache again) nor when the level may rescale.
+            // Full levels sum sigma in LDS for their first HMAX new vertices: a
+            // claim's winner at position p < HMAX enters its vertex into an LDS
+            // hash set (the keys take side X's frontier cache, read at the
+            // level's first chunk and unused until this level's bookkeeping
+            // rewrites it) and stores its own arc's count in the slot's LDS
+            // count; after the round's barrier the other arcs into the vertex
+            // add there, and each such vertex's count is stored to global
+            // memory once, in the bookkeeping.  The new vertices past HMAX are
+            // summed in global memory (the winner stores, the others add).  Not
+            // on probe levels (a retry reads the cache again) nor when the level
+            // may rescale.
             // A vertex one arc from its root has exactly one shortest path from
             // it, and the root itself one: sigma of levels 0 and 1 is 1, never
             // stored nor read (on low-diameter graphs most new vertices lie on
             // level 1 of one side).
             const bool implicit_new = lvlx == 0;    // the new level is level 1
             const bool implicit_front = lvlx <= 1;  // the frontier's sigma is 1
-            const bool lds_try = !probe && !implicit_new && fhix - flox <= TEAM && dsx <= (int64_t)ARCS * TEAM &&
-                                 bitw128(X ? fmass1 : fmass0) <= SIGMA_BITS;
+            const bool lds_try = !probe && !implicit_new && bitw128(X ? fmass1 : fmass0) <= SIGMA_BITS;
             const bool low_mass = bitw128(X ? fmass1 : fmass0) <= 63;
             int32_t *const hkeys = reinterpret_cast<int32_t *>(&sm.fsg[X][0]);  // 4 TEAM >= STAGE ints
             constexpr int32_t HMASK = STAGE - 1;
@@ -941,11 +953,11 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                             sm.cm[lane] = implicit_front ? Sigma{1u, 0u} : sigx[u];
                         }
                     }
-                    if (lds_try) {
-                        // each lane empties the key slots of its own cache entry (read above)
+                    if (lds_try && c0 == flox) {
+                        // each lane empties the key slots of its own cache entry (read
+                        // above); a slot's count is written by its winner before any add
     #pragma unroll
                         for (int j = 0; j < 4; ++j) hkeys[4 * lane + j] = -1;
-                        for (int32_t h = lane; h < STAGE; h += TEAM) sm.sw[h] = Sigma{0u, 0u};
                     }
                     int32_t tot;
                     const int32_t ex = T::excl_scan_i32(dg, &tot, redA);
@@ -1024,18 +1036,17 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                             if (claimed) {
                                 ballx[base_new + p] = w;
                                 if (p < STAGE) sm.sv[p] = w;
-                                if (lds_try) {
-                                    if (p < HMAX) hash_insert(hkeys, HMASK, w);
-                                } else if (!implicit_new) {
-                                    // summed in global memory: the claim's own arc is a
-                                    // store, the other arcs into w add after a barrier
+                                // the claim's own arc is a store (in LDS or in global
+                                // memory), the other arcs into w add after a barrier
+                                if (lds_try && p < HMAX)
+                                    sm.sw[hash_insert(hkeys, HMASK, w)] = sm.cm[ow[k]];
+                                else if (!implicit_new)
                                     sigx[w] = sm.cm[ow[k]];
-                                }
                             }
                             const bool is_meet = claimed && dyc[k] != 0u;
                             const int q = wave_append(is_meet, cnt_meet);
                             if (is_meet) meet[q] = w;
-                            add[k] = e + k * TEAM < tot && dxc[k] == code_new && (lds_try || !claimed);
+                            add[k] = e + k * TEAM < tot && dxc[k] == code_new && !claimed;
                         }
                     };
                     // sigma(w) += sigma(owner) for every arc into the new level, in
@@ -1068,18 +1079,34 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                     bool add[ARCS];
     #pragma unroll
                     for (int k = 0; k < ARCS; ++k) add[k] = false;
+                    // sigma(w) += sigma(owner) for the arcs into w that did not claim
+                    // it: in LDS if w has a slot there, else in global memory
+                    auto lds_adds = [&](const int32_t (&wv)[ARCS], const int32_t (&ow)[ARCS], bool (&add)[ARCS]) {
+    #pragma unroll
+                        for (int k = 0; k < ARCS; ++k) {
+                            if (!add[k]) continue;
+                            const int32_t h = hash_find_opt(hkeys, HMASK, wv[k]);
+                            if (h < 0) continue;  // past HMAX: stays for global_adds
+                            add[k] = false;
+                            Sigma *const q = &sm.sw[h];
+                            if (low_mass)  // no carry possible: an add without a result
+                                (void)atomicAdd((unsigned long long *)&q->lo, (unsigned long long)sm.cm[ow[k]].lo);
+                            else
+                                lds_add128(q, sm.cm[ow[k]]);
+                        }
+                    };
                     // rounds of ARCS * TEAM arcs, the same number in every lane.  A
                     // vertex's sigma is written only by the sample that reaches it
-                    // (nothing clears it afterwards): in global memory the winner of
-                    // its claim stores its own arc's count, and the other arcs into
-                    // the vertex add theirs after a barrier that follows the round's
-                    // claims (most new vertices have one predecessor: a store, no
-                    // atomic).
+                    // (nothing clears it afterwards): the winner of its claim stores
+                    // its own arc's count, and the other arcs into the vertex add
+                    // theirs after a barrier that follows the round's claims (most
+                    // new vertices have one predecessor: a store, no atomic).
                     const int32_t rounds = (tot + ARCS * TEAM - 1) / (ARCS * TEAM);
                     for (int32_t r = 0; r < rounds; ++r) {
                         claim_round(r * ARCS * TEAM + lane, wv, ow, add);
-                        if (!lds_try && !implicit_new) {  // else: one round, added below, or sigma 1
+                        if (!implicit_new) {  // else sigma 1
                             __syncthreads();
+                            if (lds_try) lds_adds(wv, ow, add);
                             global_adds(wv, ow, add);
                         }
                         // On high-diameter graphs (probe_quit) a probe whose first
@@ -1098,27 +1125,6 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                             }
                         }
                     }
-                    if (lds_try) {
-                        __syncthreads();  // the claims are done and the set is filled
-                        if (uniform_i32(*cnt_new) <= HMAX) {
-    #pragma unroll
-                            for (int k = 0; k < ARCS; ++k) {
-                                if (!add[k]) continue;
-                                Sigma *const q = &sm.sw[hash_find(hkeys, HMASK, wv[k])];
-                                if (low_mass)  // no carry possible: an add without a result
-                                    (void)atomicAdd((unsigned long long *)&q->lo, (unsigned long long)sm.cm[ow[k]].lo);
-                                else
-                                    lds_add128(q, sm.cm[ow[k]]);
-                            }
-                        } else {
-                            // too many new vertices for the set: zero their sigma,
-                            // then add in global memory
-                            for (int32_t k = lane; k < uniform_i32(*cnt_new); k += TEAM)
-                                sigx[ballx[base_new + k]] = Sigma{0u, 0u};
-                            __syncthreads();
-                            global_adds(wv, ow, add);
-                        }
-                    }
                     __syncthreads();
                     if (gave_up) break;
                 }
@@ -1134,17 +1140,19 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 sm.nmeet[lp ^ 1] = 0;
             }
             lp ^= 1;
-            // LDS-summed sigma: each new vertex's count to its global slot (at
-            // most two per lane), kept in registers for the bookkeeping below
-            const bool lds_sig = lds_try && nN <= HMAX;
+            // LDS-summed sigma (positions below HMAX <= 2 TEAM): each such new
+            // vertex's count to its global slot (at most two per lane), kept in
+            // registers for the bookkeeping below
+            const bool lds_sig = lds_try;
+            const int32_t nH = min(nN, HMAX);
             Sigma lm0{0u, 0u}, lm1{0u, 0u};
             if (lds_sig) {
-                if (lane < nN) {
+                if (lane < nH) {
                     const int32_t w = sm.sv[lane];
                     lm0 = sm.sw[hash_find(hkeys, HMASK, w)];
                     sigx[w] = lm0;
                 }
-                if (lane + TEAM < nN) {
+                if (lane + TEAM < nH) {
                     const int32_t w = sm.sv[lane + TEAM];
                     lm1 = sm.sw[hash_find(hkeys, HMASK, w)];
                     sigx[w] = lm1;
@@ -1201,9 +1209,10 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 const int32_t w2 = two ? (staged_new ? sm.sv[k2] : ballx[base_new + k2]) : w;
                 const int32_t rs = row_ptr[w], re = row_ptr[w + 1];
                 const int32_t rs2 = row_ptr[w2], re2 = row_ptr[w2 + 1];
-                // (an LDS-summed level has nN <= 2 TEAM: k = lane, k2 = lane + TEAM)
-                const Sigma m = implicit_new ? Sigma{1u, 0u} : (lds_sig ? lm0 : sigx[w]);
-                const Sigma m2 = implicit_new ? Sigma{1u, 0u} : (lds_sig ? lm1 : sigx[w2]);
+                // (LDS-summed positions are below HMAX <= 2 TEAM: the first pass,
+                // k = lane and k2 = lane + TEAM)
+                const Sigma m = implicit_new ? Sigma{1u, 0u} : ((lds_sig && k < nH) ? lm0 : sigx[w]);
+                const Sigma m2 = implicit_new ? Sigma{1u, 0u} : ((lds_sig && k2 < nH) ? lm1 : sigx[w2]);
                 const int32_t dg = re - rs;
                 ds += (uint64_t)dg;
                 ms += to128(m);
