@@ -94,20 +94,32 @@ def _double_star(a, b):
     return G.from_edges(2 + a + b, np.array(u), np.array(v), name=f"dstar{a}_{b}")
 
 
+def _layered(a, b):
+    """Vertex 0 joined to a layer of a vertices, each joined to all of a layer
+    of b vertices: every vertex of the last layer has a predecessors."""
+    u = [0] * a
+    v = list(range(1, 1 + a))
+    for i in range(1, 1 + a):
+        u += [i] * b
+        v += list(range(1 + a, 1 + a + b))
+    return G.from_edges(1 + a + b, np.array(u), np.array(v), name=f"layered{a}_{b}")
+
+
 @pytest.mark.parametrize("team", [64, 256])
 @pytest.mark.parametrize("probe", [-1, 1 << 40])
 def test_level_sigma_paths(team, probe):
-    """Levels whose sigma is summed in LDS (one-chunk frontier, one round of
-    arcs, at most STAGE/2 new vertices), levels that fall back to global adds
-    after the claims (a center's expansion with the probe off: a new level of
-    up to 1500 leaves in one round), and multi-chunk levels (a grid's wide
-    rings), with the meeting probe on (auto) and off."""
+    """A full level sums sigma in LDS for its first STAGE/2 new vertices and in
+    global memory past them: levels of up to 1500 leaves with one predecessor
+    each (a center's expansion with the probe off), levels whose vertices have
+    many predecessors over many rounds of arcs and over several frontier chunks
+    (layered graphs, a complete bipartite graph), and multi-chunk levels (a
+    grid's wide rings), with the meeting probe on (auto) and off."""
     # double stars: with the probe off, the smaller center is expanded in
-    # full: 1000 or 600 new vertices (beyond STAGE/2 for any team: global adds)
-    # or 300 (LDS for 256-lane teams)
+    # full: 1000 or 600 new vertices (past STAGE/2 for any team) or 300
     cases = [(_double_star(1500, 1000), 0.1, 100), (_double_star(700, 600), 0.1, 100),
              (_double_star(400, 300), 0.1, 64), (G.grid_graph(40, 40), 0.05, 200),
-             (G.complete_bipartite(3, 700), 0.1, 50)]
+             (G.complete_bipartite(3, 700), 0.1, 50), (_layered(150, 400), 0.1, 100),
+             (_layered(60, 1200), 0.1, 100)]
     for g, eps, n_check in cases:
         print(f"case {g.name} team={team} probe_min={probe}", flush=True)
         for seed in (2, 3):
