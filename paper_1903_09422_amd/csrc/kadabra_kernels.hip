@@ -496,43 +496,29 @@ __device__ __forceinline__ void pick_by_id_prefix64(const int32_t *sv, const Sig
     }
 }
 
-// An open-addressing set of vertex ids in LDS: mask + 1 slots (a power of
-// two), -1 = empty, linear probing.  Filled to at most half, so every probe
-// sequence ends.
+// An open-addressing map in LDS from the vertices of a new level to their
+// positions in it: `mask + 1` slots (a power of two), -1 = empty, linear
+// probing; a slot holds a position p, whose vertex is ids[p] (the level's
+// staged ids).  Filled to at most half, so every probe sequence ends.
 __device__ __forceinline__ int32_t hash_slot(int32_t w, int32_t mask)
 {
     return (int32_t)(((uint32_t)w * 0x9E3779B1u) >> 16) & mask;
 }
-__device__ __forceinline__ int32_t hash_insert(int32_t *keys, int32_t mask, int32_t w)
+__device__ __forceinline__ void pos_insert(int32_t *tab, int32_t mask, int32_t w, int32_t p)
 {
     int32_t h = hash_slot(w, mask);
-    while (atomicCAS(&keys[h], -1, w) != -1) h = (h + 1) & mask;
-    return h;
+    while (atomicCAS(&tab[h], -1, p) != -1) h = (h + 1) & mask;
 }
-// w's slot, or -1 if w is not in the set
-__device__ __forceinline__ int32_t hash_find_opt(const int32_t *keys, int32_t mask, int32_t w)
+// w's position, or -1 if w is not in the map
+__device__ __forceinline__ int32_t pos_find(const int32_t *tab, const int32_t *ids, int32_t mask, int32_t w)
 {
     int32_t h = hash_slot(w, mask);
     for (;;) {
-        const int32_t k = keys[h];
-        if (k == w) return h;
-        if (k == -1) return -1;
+        const int32_t q = tab[h];
+        if (q < 0) return -1;
+        if (ids[q] == w) return q;
         h = (h + 1) & mask;
     }
-}
-__device__ __forceinline__ int32_t hash_find(const int32_t *keys, int32_t mask, int32_t w)
-{
-    int32_t h = hash_slot(w, mask);
-    while (keys[h] != w) h = (h + 1) & mask;
-    return h;
-}
-
-// *p += v for a 128-bit count in LDS
-__device__ __forceinline__ void lds_add128(Sigma *p, Sigma v)
-{
-    const uint64_t o = atomicAdd((unsigned long long *)&p->lo, (unsigned long long)v.lo);
-    const uint64_t hi = v.hi + ((o + v.lo) < o ? 1u : 0u);
-    if (hi) atomicAdd((unsigned long long *)&p->hi, (unsigned long long)hi);
 }
 
 // Zeroes the code word of every vertex in ball[0, len).  (Sigma needs no
@@ -796,28 +782,27 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
             int32_t *const cnt_new = &sm.nnext[lp];
             int32_t *const cnt_meet = &sm.nmeet[lp];
             const bool fcx = X ? fc1 : fc0;  // then the frontier is one chunk
-            // Full levels sum sigma in LDS for their first HMAX new vertices: a
-            // claim's winner at position p < HMAX enters its vertex into an LDS
-            // hash set (the keys take side X's frontier cache, read at the
-            // level's first chunk and unused until this level's bookkeeping
-            // rewrites it) and stores its own arc's count in the slot's LDS
-            // count; after the round's barrier the other arcs into the vertex
-            // add there, and each such vertex's count is stored to global
-            // memory once, in the bookkeeping.  The new vertices past HMAX are
-            // summed in global memory (the winner stores, the others add).  Not
-            // on probe levels (a retry reads the cache again) nor when the level
-            // may rescale.
+            // Full levels whose frontier mass is below 2^63 (no count of the new
+            // level leaves 64 bits) sum sigma in LDS for their first STAGE new
+            // vertices: the staging area's counts hold a map from vertex to
+            // position (2 STAGE slots) and a 64-bit count per position.  The
+            // claim's winner at position p < STAGE enters w -> p and stores its
+            // own arc's count at p; after the round's barrier the other arcs
+            // into w add there; each such count is stored to global memory once,
+            // in the bookkeeping.  The new vertices past STAGE are summed in
+            // global memory (the winner stores, the others add).  Not on probe
+            // levels.
             // A vertex one arc from its root has exactly one shortest path from
             // it, and the root itself one: sigma of levels 0 and 1 is 1, never
             // stored nor read (on low-diameter graphs most new vertices lie on
             // level 1 of one side).
             const bool implicit_new = lvlx == 0;    // the new level is level 1
             const bool implicit_front = lvlx <= 1;  // the frontier's sigma is 1
-            const bool lds_try = !probe && !implicit_new && bitw128(X ? fmass1 : fmass0) <= SIGMA_BITS;
             const bool low_mass = bitw128(X ? fmass1 : fmass0) <= 63;
-            int32_t *const hkeys = reinterpret_cast<int32_t *>(&sm.fsg[X][0]);  // 4 TEAM >= STAGE ints
-            constexpr int32_t HMASK = STAGE - 1;
-            constexpr int32_t HMAX = STAGE / 2;  // at most half of the slots are filled
+            const bool lds_try = !probe && !implicit_new && low_mass;
+            int32_t *const ptab = reinterpret_cast<int32_t *>(&sm.sw[0]);               // [2 STAGE]
+            uint64_t *const pval = reinterpret_cast<uint64_t *>(&sm.sw[0]) + STAGE;     // [STAGE]
+            constexpr int32_t PMASK = 2 * STAGE - 1;
             if (PULL && probe) {
                 // Pull form of the meeting probe: the rows of Y's frontier are
                 // scanned for neighbours on X's frontier.  Such a neighbour p
@@ -954,10 +939,9 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                         }
                     }
                     if (lds_try && c0 == flox) {
-                        // each lane empties the key slots of its own cache entry (read
-                        // above); a slot's count is written by its winner before any add
-    #pragma unroll
-                        for (int j = 0; j < 4; ++j) hkeys[4 * lane + j] = -1;
+                        // an empty map; a position's count is written by its winner
+                        // before any add
+                        for (int32_t h = lane; h < 2 * STAGE; h += TEAM) ptab[h] = -1;
                     }
                     int32_t tot;
                     const int32_t ex = T::excl_scan_i32(dg, &tot, redA);
@@ -1038,10 +1022,12 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                                 if (p < STAGE) sm.sv[p] = w;
                                 // the claim's own arc is a store (in LDS or in global
                                 // memory), the other arcs into w add after a barrier
-                                if (lds_try && p < HMAX)
-                                    sm.sw[hash_insert(hkeys, HMASK, w)] = sm.cm[ow[k]];
-                                else if (!implicit_new)
+                                if (lds_try && p < STAGE) {
+                                    pval[p] = sm.cm[ow[k]].lo;
+                                    pos_insert(ptab, PMASK, w, p);
+                                } else if (!implicit_new) {
                                     sigx[w] = sm.cm[ow[k]];
+                                }
                             }
                             const bool is_meet = claimed && dyc[k] != 0u;
                             const int q = wave_append(is_meet, cnt_meet);
@@ -1085,14 +1071,11 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
     #pragma unroll
                         for (int k = 0; k < ARCS; ++k) {
                             if (!add[k]) continue;
-                            const int32_t h = hash_find_opt(hkeys, HMASK, wv[k]);
-                            if (h < 0) continue;  // past HMAX: stays for global_adds
+                            const int32_t q = pos_find(ptab, sm.sv, PMASK, wv[k]);
+                            if (q < 0) continue;  // past STAGE: stays for global_adds
                             add[k] = false;
-                            Sigma *const q = &sm.sw[h];
-                            if (low_mass)  // no carry possible: an add without a result
-                                (void)atomicAdd((unsigned long long *)&q->lo, (unsigned long long)sm.cm[ow[k]].lo);
-                            else
-                                lds_add128(q, sm.cm[ow[k]]);
+                            // no carry possible (mass below 2^63): an add without a result
+                            (void)atomicAdd((unsigned long long *)&pval[q], (unsigned long long)sm.cm[ow[k]].lo);
                         }
                     };
                     // rounds of ARCS * TEAM arcs, the same number in every lane.  A
@@ -1140,24 +1123,16 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 sm.nmeet[lp ^ 1] = 0;
             }
             lp ^= 1;
-            // LDS-summed sigma (positions below HMAX <= 2 TEAM): each such new
-            // vertex's count to its global slot (at most two per lane), kept in
-            // registers for the bookkeeping below
+            // LDS-summed sigma (positions below STAGE): each such new vertex's
+            // count to its global slot; the bookkeeping below reads them by
+            // position from LDS
             const bool lds_sig = lds_try;
-            const int32_t nH = min(nN, HMAX);
-            Sigma lm0{0u, 0u}, lm1{0u, 0u};
+            const int32_t nH = min(nN, STAGE);
             if (lds_sig) {
-                if (lane < nH) {
-                    const int32_t w = sm.sv[lane];
-                    lm0 = sm.sw[hash_find(hkeys, HMASK, w)];
-                    sigx[w] = lm0;
-                }
-                if (lane + TEAM < nH) {
-                    const int32_t w = sm.sv[lane + TEAM];
-                    lm1 = sm.sw[hash_find(hkeys, HMASK, w)];
-                    sigx[w] = lm1;
-                }
-                __syncthreads();  // counts stored, set read: the cache may be rewritten
+                for (int32_t k = lane; k < nH; k += TEAM) sigx[sm.sv[k]] = Sigma{pval[k], 0u};
+                // counts read: a meeting draw may restage the area (the
+                // bookkeeping below reads the counts again, the staging not)
+                __syncthreads();
             }
             if (probe && nM == 0) {  // no meeting on this level: expand it in full
                 retry = true;
@@ -1209,10 +1184,8 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
                 const int32_t w2 = two ? (staged_new ? sm.sv[k2] : ballx[base_new + k2]) : w;
                 const int32_t rs = row_ptr[w], re = row_ptr[w + 1];
                 const int32_t rs2 = row_ptr[w2], re2 = row_ptr[w2 + 1];
-                // (LDS-summed positions are below HMAX <= 2 TEAM: the first pass,
-                // k = lane and k2 = lane + TEAM)
-                const Sigma m = implicit_new ? Sigma{1u, 0u} : ((lds_sig && k < nH) ? lm0 : sigx[w]);
-                const Sigma m2 = implicit_new ? Sigma{1u, 0u} : ((lds_sig && k2 < nH) ? lm1 : sigx[w2]);
+                const Sigma m = implicit_new ? Sigma{1u, 0u} : ((lds_sig && k < nH) ? Sigma{pval[k], 0u} : sigx[w]);
+                const Sigma m2 = implicit_new ? Sigma{1u, 0u} : ((lds_sig && k2 < nH) ? Sigma{pval[k2], 0u} : sigx[w2]);
                 const int32_t dg = re - rs;
                 ds += (uint64_t)dg;
                 ms += to128(m);
