@@ -552,7 +552,8 @@ __global__ __launch_bounds__(TEAM) __attribute__((amdgpu_waves_per_eu(4))) void 
     // step found no predecessor) and its cause is not known: it is not built.
     static_assert(TEAM != 64, "phase timers are not available for 64-lane teams");
 #endif
-    constexpr int ARCS = (TEAM == 64) ? 4 : 8;     // arcs in flight per lane in a level expansion
+    constexpr int ARCS = (TEAM == 64) ? 4 : (TEAM == 256) ? 6 : 8;  // arcs in flight per lane in a level
+                                                                   // expansion (measured per team size)
     constexpr int STAGE = Cap<TEAM>::STAGE;
     __shared__ SampleShared<TEAM> sm;
     const int lane = threadIdx.x;
